@@ -1,0 +1,169 @@
+/*
+ * ttn.h -- C ABI of the MI355X (gfx950) tree-tensor-network TDVP library.
+ *
+ * The library time-evolves a binary tree tensor network (TTN) under the
+ * time-dependent Rydberg Hamiltonian of arXiv 2210.03763 with single-site
+ * TDVP, entirely on one GPU.  Paper anchors:
+ *   - Hamiltonian: Eq. (eq:ham) with the van der Waals coupling Eq. (eq:c6),
+ *     Sec. "Modeling 88Sr quantum computers on two-dimensional grids".  Read
+ *     here as   H(t) = sum_i [Omega_i(t)/2 (|1><r| + h.c.) - Delta_i(t) |r><r|
+ *                   + leak_ratio Omega_i(t)/2 (|leak><r| + h.c.)]
+ *                   + sum_{i<j} C6 / |x_i - x_j|^6 n_i n_j ,  n = |r><r| ;
+ *   - TTN with Hilbert-curve leaf order, tensor product operator with all
+ *     two-body terms, TDVP time evolution, bond dimension chi, interaction
+ *     cut-off radius: Sec. "Tensor network simulations";
+ *   - fidelity F = |<psi(tau)|psi_GHZ>|^2: Sec. on GHZ state preparation;
+ *   - per-layer piecewise pulses, idle atoms undriven: Sec. "Tensor network
+ *     simulations".
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers in host arrays are interleaved (re, im) doubles.
+ *   - Sites are numbered s = 0..N-1; the caller gives their positions.  The
+ *     tree has N = 2^K leaves; leaf k holds site leaf_order[k]; bottom nodes
+ *     own leaves (2j, 2j+1); link dimension above a subtree of s sites is
+ *     min(chi, d^s, d^(N-s)).  Node tensors T[l, r, p] (left child, right
+ *     child, parent), l fastest; nodes numbered level by level from the
+ *     bottom (level 0) to the root.
+ *   - Step n (counted from ttn_init) applies the gate events scheduled at n,
+ *     freezes H at t = (n + 1/2) dt, and performs S(dt/2) followed by its
+ *     exact reverse; events scheduled at the step count reached at the end of
+ *     a ttn_tdvp_step call are applied before it returns.
+ *   - Every call enqueues work on the stream given to ttn_init and returns
+ *     after the stream is synchronised (calls return host values).
+ *   - Errors: a negative status.  No C++ exception crosses this boundary.
+ *     TTN_EINVAL leaves the handle unchanged.  TTN_ENUMERIC (NaN/Inf, a
+ *     non-positive Cholesky pivot in a QR gauge move, norm drift) poisons the
+ *     handle: every later call except ttn_last_error/ttn_destroy returns
+ *     TTN_ESTATE.  ttn_last_error gives a text.  A handle is not thread
+ *     safe; distinct handles are independent.
+ */
+#ifndef TTN_H
+#define TTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTN_OK 0
+#define TTN_EINVAL -1
+#define TTN_ENOMEM -2
+#define TTN_EDEVICE -3
+#define TTN_ENUMERIC -4
+#define TTN_ESTATE -5
+#define TTN_ENOTSUP -6
+
+/* Arithmetic of the effective-Hamiltonian contractions (the H_eff and
+ * K_eff matvecs).  Lanczos scalars and re-orthogonalisation, the small
+ * tridiagonal exponential, QR gauge moves, environment updates and the
+ * master node tensors are FP64 in every mode. */
+#define TTN_PREC_FP64 0
+#define TTN_PREC_FP32 1
+
+typedef struct ttn_handle ttn_handle;
+
+typedef struct {
+    int32_t n_sites;        /* N = 2^K, 2 <= N <= 1024                       */
+    int32_t d;              /* local dimension: 3 {0,1,r} or 4 {0,1,r,leak}   */
+    int32_t chi;            /* maximal bond dimension, 1 <= chi <= 256        */
+    int32_t krylov_dim;     /* Lanczos dimension m, 1 <= m <= 16              */
+    int32_t precision;      /* TTN_PREC_*                                     */
+    int32_t reserved;
+    double c6;              /* van der Waals coefficient (a = 1 units)         */
+    double r_cut;           /* pairs farther than r_cut dropped; <= 0: all     */
+    double leak_ratio;      /* |r>-|leak> coupling relative to Omega/2 (d = 4) */
+    const double* pos_xy;   /* host [N][2] positions                          */
+    const int32_t* leaf_order; /* host [N], a permutation of 0..N-1           */
+    const double* init_product; /* host [N][d] complex: one local state per site */
+    double dress_eps;       /* dressing amplitude epsilon (>= 0)               */
+    const double* dress_noise;  /* host complex stream G, node blocks level by
+                                   level, l fastest; may be NULL if eps == 0 */
+    int64_t dress_noise_len;    /* complex elements in dress_noise           */
+} ttn_config;
+
+/* Per-step diagnostics, filled by ttn_tdvp_step when stats != NULL. */
+typedef struct {
+    double norm2;           /* ||psi||^2 after the step                       */
+    double energy;          /* <psi|H(t_n + dt/2)|psi> after the step         */
+    double min_r_diag;      /* smallest R_kk of every QR in the step           */
+    int32_t min_krylov;     /* smallest Krylov dimension reached (breakdown)   */
+    int32_t reserved;
+} ttn_step_stats;
+
+/* Device bytes the caller must provide to ttn_init for this configuration
+ * (one allocation, 256-byte aligned).  Returns TTN_EINVAL for a bad config. */
+int ttn_workspace_query(const ttn_config* cfg, size_t* device_bytes);
+
+/* Builds the tree, the van der Waals matrix (Eq. c6) and the initial
+ * state: isometries carrying the product state init_product, completed by
+ * Gram-Schmidt of unit vectors in order and, if dress_eps > 0, dressed as
+ * T += eps G / sqrt(D_l D_r); then QR-canonicalised toward the root and
+ * normalised.  d_workspace is caller-owned device memory of at least the
+ * queried size that must outlive the handle; hip_stream is a hipStream_t
+ * (NULL: the null stream).  Host arrays are copied.  On success *out is a
+ * library-owned handle released by ttn_destroy. */
+int ttn_init(const ttn_config* cfg, void* d_workspace, size_t workspace_bytes,
+             void* hip_stream, ttn_handle** out);
+
+/* Piecewise-constant drive and exact local gate events.
+ *   seg_edges [n_seg + 1] ascending times; segment s covers
+ *   [seg_edges[s], seg_edges[s+1]); outside all segments the drive is zero.
+ *   omega, delta [N][n_seg] (site-major).
+ *   Event e applies the d x d unitary ev_u[e] (complex, row-major U[a][b])
+ *   to site ev_site[e] at step ev_step[e].
+ * Replaces any earlier program; events at steps already passed are ignored. */
+int ttn_set_pulses(ttn_handle* h, int32_t n_seg, const double* seg_edges,
+                   const double* omega, const double* delta, int32_t n_events,
+                   const int32_t* ev_step, const int32_t* ev_site, const double* ev_u);
+
+/* n_steps TDVP steps of size dt (dt must not change between calls).
+ * stats: host array [n_steps] or NULL. */
+int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* stats);
+
+/* Fidelity with the GHZ-type target (|0..0> + |1_S 0_rest>)/sqrt 2 where S
+ * are the n_target sites listed (S = all sites gives the GHZ state; the
+ * centre atom plus its four neighbours gives the five-qubit repetition code
+ * with the other atoms idle).  F = |<target|psi>|^2; overlap = <target|psi>. */
+int ttn_fidelity(ttn_handle* h, int32_t n_target, const int32_t* target_sites,
+                 double* F, double overlap[2]);
+
+/* ||psi||^2 and <psi|H|psi> with H at the last step's midpoint. */
+int ttn_observables(ttn_handle* h, double* norm2, double* energy);
+
+/* <psi|O_site|psi> for a d x d complex operator (row-major O[a][b]). */
+int ttn_local_expectation(ttn_handle* h, int32_t site, const double* op, double out[2]);
+
+/* <psi_a|psi_b> for two handles of the same shape (same N, d, chi, leaf
+ * order); used for the state infidelity C = 1 - |<a|b>|^2 (Tab. conv8x8). */
+int ttn_overlap(ttn_handle* a, ttn_handle* b, double out[2]);
+
+/* Copies every node tensor to host, complex interleaved, in the node order
+ * and layout above; len = complex elements available.  Returns the number
+ * of complex elements needed when host == NULL. */
+int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len);
+
+/* Gradient of the fidelity with respect to the pulse table (reverse mode
+ * through the discrete evolution).  Not available in this build:
+ * returns TTN_ENOTSUP. */
+int ttn_backward(ttn_handle* h, double dF, double* grad_omega, double* grad_delta);
+
+/* Checks the launch plan of a configuration without a device: walks
+ * initialisation, n_steps TDVP steps of a one-segment program with a gate on
+ * every site, the fidelity, a local expectation and a self overlap, and
+ * verifies that every kernel operand stays inside its workspace allocation.
+ * No device memory is touched.  msg (may be NULL) receives "ok" or the first
+ * violation.  Not thread safe with concurrent device calls of this library. */
+int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t msg_len);
+
+int ttn_destroy(ttn_handle* h);
+/* Text of the last error of h; with h == NULL, of the last failed ttn_init
+ * on this thread. */
+const char* ttn_last_error(const ttn_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTN_H */

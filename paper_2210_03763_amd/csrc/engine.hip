@@ -1,0 +1,1569 @@
+// Host orchestration of single-site TDVP on a binary tree tensor network
+// (arXiv 2210.03763, Sec. "Tensor network simulations") and the C ABI of
+// include/ttn.h.  Every arithmetic step on the state runs in the device
+// kernels of kernels.hip; the host only walks the tree and enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ttn.h"
+#include "ttn_internal.h"
+
+using namespace ttn;
+
+namespace {
+
+constexpr double LANCZOS_TOL = 1e-12;     // beta_{j+1} <= tol (|alpha_j| + beta_j)
+constexpr double COMPLETION_TOL = 1e-8;   // Gram-Schmidt acceptance for initial isometries
+constexpr int RED_BLOCKS = 256;
+
+struct StatusError {
+    int code;
+    std::string msg;
+};
+
+#define HIPCHECK(x)                                                                       \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess)                                                             \
+            throw StatusError{TTN_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures.
+struct Bump {
+    char* base;
+    size_t off = 0, cap;
+    std::vector<Region>* regions;
+    Bump(void* b, size_t c, std::vector<Region>* r = nullptr) : base((char*)b), cap(c), regions(r) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        if (regions && base) regions->push_back(Region{(uintptr_t)p, (uintptr_t)p + count * sizeof(T)});
+        off += count * sizeof(T);
+        if (base && off > cap) throw StatusError{TTN_ENOMEM, "workspace too small"};
+        return p;
+    }
+};
+
+struct Event {
+    int step, site;
+    double* U;   // device, d x d planar column-major
+    bool applied;
+};
+
+}  // namespace
+
+struct ttn_handle {
+    // configuration
+    int N = 0, d = 0, chi = 0, m = 0, prec = 0;
+    double c6 = 1, rcut = 0, leak = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool poisoned = false;
+    // tree
+    int K = 0, n_nodes = 0, root = 0;
+    std::vector<int> level, idx, parent, ch0, ch1, DL, DR, DP, sfirst, scount;
+    std::vector<int> leaf_site;
+    std::vector<double> V;   // N x N
+    // device state
+    std::vector<double*> T, up, dn, vLR, vRL;
+    double* leafblk = nullptr;
+    int* d_leaf_site = nullptr;
+    // scratch
+    int64_t nmax = 0, stack_max = 0, env_max = 0;
+    int max_sites = 0, Dmax = 0;
+    double *X = nullptr, *W = nullptr, *Vk = nullptr, *Qtmp = nullptr, *Ttmp = nullptr;
+    float *Xf = nullptr, *Yf = nullptr;
+    double *Bstk = nullptr, *Astk = nullptr;
+    float *Lf = nullptr, *Rf = nullptr, *Bf = nullptr, *Wf = nullptr;
+    double *G = nullptr, *Linv = nullptr, *R1 = nullptr, *Rq = nullptr, *Cb = nullptr,
+           *cholwork = nullptr;
+    double* red = nullptr;
+    LanczosDev *lz = nullptr, *lz_obs = nullptr;
+    StepDev* st = nullptr;
+    GemmScratch gs;
+    double *ov_vec = nullptr, *ov_leaf = nullptr, *ov_M = nullptr, *ov_Y1 = nullptr, *ov_Y2 = nullptr;
+    double* opbuf = nullptr;
+    // program
+    int n_seg = 0;
+    std::vector<double> edges;
+    double *d_omega = nullptr, *d_delta = nullptr;
+    double* d_evU = nullptr;
+    std::vector<Event> events;
+    int64_t step_count = 0;
+    double dt = 0;
+    bool dt_set = false;
+    int cur_seg = -2;
+    size_t ws_bytes = 0;
+    // host staging for asynchronous copies
+    LanczosDev h_lzinit{}, h_lzout{};
+    StepDev h_stepinit{}, h_stepout{};
+    // workspace regions for launch extent checks (sorted by address)
+    std::vector<Region> regions;
+    bool dry = false;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// tree
+// ---------------------------------------------------------------------------
+int64_t capped_pow(int d, int e, int64_t cap) {
+    int64_t v = 1;
+    for (int i = 0; i < e; ++i) {
+        v *= d;
+        if (v >= cap) return cap;
+    }
+    return v;
+}
+
+int link_dim(const ttn_handle* h, int s) {
+    if (s >= h->N) return 1;
+    int64_t a = capped_pow(h->d, s, h->chi + 1), b = capped_pow(h->d, h->N - s, h->chi + 1);
+    return (int)std::min<int64_t>({(int64_t)h->chi, a, b});
+}
+
+void build_tree(ttn_handle* h) {
+    int K = 0;
+    while ((1 << K) < h->N) ++K;
+    h->K = K;
+    std::vector<int> off(K);
+    int o = 0;
+    for (int l = 0; l < K; ++l) {
+        off[l] = o;
+        o += h->N >> (l + 1);
+    }
+    h->n_nodes = o;
+    h->root = o - 1;
+    for (int l = 0; l < K; ++l)
+        for (int j = 0; j < (h->N >> (l + 1)); ++j) {
+            h->level.push_back(l);
+            h->idx.push_back(j);
+            h->parent.push_back(l + 1 < K ? off[l + 1] + j / 2 : -1);
+            h->ch0.push_back(l == 0 ? -1 : off[l - 1] + 2 * j);
+            h->ch1.push_back(l == 0 ? -1 : off[l - 1] + 2 * j + 1);
+            const int dc = l == 0 ? h->d : link_dim(h, 1 << l);
+            h->DL.push_back(dc);
+            h->DR.push_back(dc);
+            h->DP.push_back(link_dim(h, 1 << (l + 1)));
+            const int w = 1 << (l + 1);
+            h->sfirst.push_back(j * w);
+            h->scount.push_back(w);
+        }
+    for (int v = 0; v < h->n_nodes; ++v)
+        if ((int64_t)h->DP[v] > (int64_t)h->DL[v] * h->DR[v])
+            throw StatusError{TTN_EINVAL, "inconsistent link dimensions"};
+}
+
+inline int64_t nsize(const ttn_handle* h, int v) { return (int64_t)h->DL[v] * h->DR[v] * h->DP[v]; }
+inline bool is_bottom(const ttn_handle* h, int v) { return h->level[v] == 0; }
+inline int leg_in_parent(const ttn_handle* h, int v) { return h->idx[v] & 1; }
+inline int sites_left(const ttn_handle* h, int v) { return h->scount[v] / 2; }
+
+// plan every buffer; with ws == nullptr only sizes are accumulated
+void plan(ttn_handle* h, Bump& b) {
+    const int nn = h->n_nodes;
+    h->T.assign(nn, nullptr);
+    h->up.assign(nn, nullptr);
+    h->dn.assign(nn, nullptr);
+    h->vLR.assign(nn, nullptr);
+    h->vRL.assign(nn, nullptr);
+    h->nmax = 0;
+    h->stack_max = 0;
+    h->Dmax = h->d;
+    h->max_sites = 0;
+    h->env_max = 0;
+    for (int v = 0; v < nn; ++v) {
+        const int64_t n = nsize(h, v);
+        h->nmax = std::max(h->nmax, n);
+        h->stack_max = std::max(h->stack_max, (int64_t)(1 + h->scount[v]) * n);
+        h->Dmax = std::max({h->Dmax, h->DL[v], h->DR[v], h->DP[v]});
+        h->max_sites = std::max(h->max_sites, h->scount[v]);
+        h->T[v] = b.take<double>(2 * n);
+        const int64_t e = (int64_t)(1 + h->scount[v]) * h->DP[v] * h->DP[v];
+        h->env_max = std::max(h->env_max, e);
+        if (v != h->root) {
+            h->up[v] = b.take<double>(2 * e);
+            h->dn[v] = b.take<double>(2 * e);
+        }
+        const int sL = sites_left(h, v);
+        h->vLR[v] = b.take<double>(2 * (int64_t)sL * sL);
+        h->vRL[v] = b.take<double>(2 * (int64_t)sL * sL);
+    }
+    // bond stacks (sites below v, size DP^2) are bounded by stack_max as well
+    for (int v = 0; v < nn; ++v)
+        h->stack_max = std::max(h->stack_max, (int64_t)(1 + h->scount[v]) * h->DP[v] * h->DP[v]);
+    const int64_t D2 = (int64_t)h->Dmax * h->Dmax;
+    const int64_t smax = h->max_sites + 1;
+    h->leafblk = b.take<double>((int64_t)h->N * 4 * h->d * h->d);
+    h->d_leaf_site = b.take<int>(h->N);
+    h->X = b.take<double>(2 * h->stack_max);
+    h->W = b.take<double>(2 * h->nmax);
+    h->Vk = b.take<double>(2 * h->nmax * (h->m + 1));
+    h->Qtmp = b.take<double>(2 * h->nmax);
+    h->Ttmp = b.take<double>(2 * h->nmax);
+    if (h->prec == TTN_PREC_FP32) {
+        h->Xf = b.take<float>(2 * h->stack_max);
+        h->Yf = b.take<float>(2 * h->nmax);
+        h->Lf = b.take<float>(2 * smax * D2);
+        h->Rf = b.take<float>(2 * smax * D2);
+        h->Bf = b.take<float>(2 * smax * D2);
+        h->Wf = b.take<float>(2 * smax * D2);
+    }
+    h->Bstk = b.take<double>(2 * smax * D2);
+    h->Astk = b.take<double>(2 * smax * D2);
+    h->G = b.take<double>(2 * D2);
+    h->Linv = b.take<double>(2 * D2);
+    h->R1 = b.take<double>(2 * D2);
+    h->Rq = b.take<double>(2 * D2);
+    h->Cb = b.take<double>(2 * D2);
+    h->cholwork = b.take<double>(2 * D2 + 64);
+    h->red = b.take<double>((int64_t)RED_BLOCKS * KRYLOV_MAX * 2 + 64);
+    h->lz = b.take<LanczosDev>(1);
+    h->lz_obs = b.take<LanczosDev>(1);
+    h->st = b.take<StepDev>(1);
+    // split-K partials: at most 1024 tiles worth of 64x64 complex outputs
+    h->gs.bytes = (int64_t)2 * 64 * 64 * 1024 * sizeof(double) * 2;
+    h->gs.partial = b.take<char>(h->gs.bytes);
+    int64_t sumDP = 0;
+    for (int v = 0; v < nn; ++v) sumDP += h->DP[v];
+    h->ov_vec = b.take<double>(2 * sumDP + 2 * 64);
+    h->ov_leaf = b.take<double>((int64_t)2 * h->N * h->d);
+    h->ov_M = b.take<double>(2 * (int64_t)nn * h->Dmax * h->Dmax);
+    h->ov_Y1 = b.take<double>(2 * h->nmax);
+    h->ov_Y2 = b.take<double>(2 * h->nmax);
+    h->opbuf = b.take<double>(2 * h->d * h->d);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM helpers on node tensors T[l, r, p] (l fastest), planar complex
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Ctx {
+    ttn_handle* h;
+    const int* skip;
+    void run(const Gemm<R>& g) {
+        char why[256];
+        if (!cgemm<R>(g, h->gs, h->stream, why, sizeof(why)))
+            throw StatusError{TTN_EINVAL, std::string("launch extent check failed: ") + why};
+    }
+};
+
+// extent check for non-GEMM launches: [p, p + count) must lie in one region
+void chk(const ttn_handle* h, const void* p, int64_t count_doubles, const char* what) {
+    const uintptr_t a = (uintptr_t)p, e = a + (uintptr_t)count_doubles * sizeof(double);
+    for (const Region& r : h->regions)
+        if (a >= r.lo && e <= r.hi) return;
+    throw StatusError{TTN_EINVAL, std::string("launch extent check failed: ") + what};
+}
+
+void sort_regions(ttn_handle* h) {
+    std::sort(h->regions.begin(), h->regions.end(), [](const Region& a, const Region& b) { return a.lo < b.lo; });
+    h->gs.regions = h->regions.data();
+    h->gs.n_regions = (int)h->regions.size();
+}
+
+void h2d(ttn_handle* h, void* dst, const void* src, size_t bytes) {
+    if (h->dry) return;
+    HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+}
+void d2h(ttn_handle* h, void* dst, const void* src, size_t bytes) {
+    if (h->dry) {
+        std::memset(dst, 0, bytes);
+        return;
+    }
+    HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+}
+void sync(ttn_handle* h) {
+    if (h->dry) return;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+// Y[.., a, ..] (+)= sum_b Op[a, b] X[.., b, ..] on leg `leg` of a (DL, DR, DP)
+// tensor; nops operators (slot stride so) act on nops tensors (stride sx, or
+// 0 for a shared X) writing nops outputs (stride sy).  trans: use Op^T;
+// conj: use conj(Op).
+template <typename R>
+void leg_apply(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int64_t sx, R* Y, int64_t sy,
+               int DL, int DR, int DP, int nops, int beta, bool conj = false, bool trans = false) {
+    const int64_t n = (int64_t)DL * DR * DP;
+    Gemm<R> g;
+    g.beta = beta;
+    g.skip = c.skip;
+    if (leg == 0) {
+        const int D = DL;
+        g.M = D;
+        g.N = DR * DP;
+        g.Kin = D;
+        g.A = Op;
+        g.a_plane = (int64_t)D * D;
+        g.sam = trans ? D : 1;
+        g.sak = trans ? 1 : D;
+        g.sab1 = so;
+        g.conjA = conj;
+        g.B = X;
+        g.b_plane = n;
+        g.sbk = 1;
+        g.sbn = DL;
+        g.sbb1 = sx;
+        g.C = Y;
+        g.c_plane = n;
+        g.scm = 1;
+        g.scn = DL;
+        g.scb1 = sy;
+        g.B1 = nops;
+    } else if (leg == 1) {
+        const int D = DR;
+        g.M = DL;
+        g.N = D;
+        g.Kin = D;
+        g.B1 = DP;
+        g.B2 = nops;
+        g.A = X;
+        g.a_plane = n;
+        g.sam = 1;
+        g.sak = DL;
+        g.sab1 = (int64_t)DL * DR;
+        g.sab2 = sx;
+        g.B = Op;
+        g.b_plane = (int64_t)D * D;
+        g.sbk = trans ? 1 : D;
+        g.sbn = trans ? D : 1;
+        g.sbb2 = so;
+        g.conjB = conj;
+        g.C = Y;
+        g.c_plane = n;
+        g.scm = 1;
+        g.scn = DL;
+        g.scb1 = (int64_t)DL * DR;
+        g.scb2 = sy;
+    } else {
+        const int D = DP;
+        g.M = DL * DR;
+        g.N = D;
+        g.Kin = D;
+        g.A = X;
+        g.a_plane = n;
+        g.sam = 1;
+        g.sak = (int64_t)DL * DR;
+        g.sab1 = sx;
+        g.B = Op;
+        g.b_plane = (int64_t)D * D;
+        g.sbk = trans ? 1 : D;
+        g.sbn = trans ? D : 1;
+        g.sbb1 = so;
+        g.conjB = conj;
+        g.C = Y;
+        g.c_plane = n;
+        g.scm = 1;
+        g.scn = (int64_t)DL * DR;
+        g.scb1 = sy;
+        g.B1 = nops;
+    }
+    c.run(g);
+}
+
+// Y (+)= sum_{k<cnt} Op_k on leg of X_k (operator slots stride so, tensor slots
+// stride sx) -- one GEMM with a two-level contraction index.
+template <typename R>
+void leg_apply_sum(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int64_t sx, R* Y, int DL,
+                   int DR, int DP, int cnt, int beta) {
+    if (cnt <= 0) return;
+    const int64_t n = (int64_t)DL * DR * DP;
+    Gemm<R> g;
+    g.beta = beta;
+    g.skip = c.skip;
+    g.Kout = cnt;
+    if (leg == 1) {
+        const int D = DR;
+        g.M = DL;
+        g.N = D;
+        g.Kin = D;
+        g.B1 = DP;
+        g.A = X;
+        g.a_plane = n;
+        g.sam = 1;
+        g.sak = DL;
+        g.sako = sx;
+        g.sab1 = (int64_t)DL * DR;
+        g.B = Op;
+        g.b_plane = (int64_t)D * D;
+        g.sbk = D;
+        g.sbn = 1;
+        g.sbko = so;
+        g.C = Y;
+        g.c_plane = n;
+        g.scm = 1;
+        g.scn = DL;
+        g.scb1 = (int64_t)DL * DR;
+    } else if (leg == 2) {
+        const int D = DP;
+        g.M = DL * DR;
+        g.N = D;
+        g.Kin = D;
+        g.A = X;
+        g.a_plane = n;
+        g.sam = 1;
+        g.sak = (int64_t)DL * DR;
+        g.sako = sx;
+        g.B = Op;
+        g.b_plane = (int64_t)D * D;
+        g.sbk = D;
+        g.sbn = 1;
+        g.sbko = so;
+        g.C = Y;
+        g.c_plane = n;
+        g.scm = 1;
+        g.scn = (int64_t)DL * DR;
+    } else {
+        // L leg: Y[a, .] = sum_k sum_b Op_k[a, b] X_k[b, .]
+        const int D = DL;
+        g.M = D;
+        g.N = DR * DP;
+        g.Kin = D;
+        g.A = Op;
+        g.a_plane = (int64_t)D * D;
+        g.sam = 1;
+        g.sak = D;
+        g.sako = so;
+        g.B = X;
+        g.b_plane = n;
+        g.sbk = 1;
+        g.sbko = sx;
+        g.sbn = DL;
+        g.C = Y;
+        g.c_plane = n;
+        g.scm = 1;
+        g.scn = DL;
+    }
+    c.run(g);
+}
+
+// E_k[a, b] = sum over the other legs of conj(Q[.., a, ..]) X_k[.., b, ..]
+// for nx tensors X_k (stride sx); outputs D x D column-major (stride se).
+void leg_gram(Ctx<double>& c, int leg, const double* Q, const double* X, int64_t sx, double* E,
+              int64_t se, int DL, int DR, int DP, int nx) {
+    const int64_t n = (int64_t)DL * DR * DP;
+    Gemm<double> g;
+    g.skip = c.skip;
+    g.conjA = true;
+    g.A = Q;
+    g.a_plane = n;
+    g.B = X;
+    g.b_plane = n;
+    g.sbb1 = sx;
+    g.C = E;
+    g.scm = 1;
+    g.scb1 = se;
+    g.B1 = nx;
+    if (leg == 2) {
+        const int D = DP;
+        g.M = g.N = D;
+        g.Kin = DL * DR;
+        g.sam = (int64_t)DL * DR;
+        g.sak = 1;
+        g.sbk = 1;
+        g.sbn = (int64_t)DL * DR;
+        g.c_plane = (int64_t)D * D;
+        g.scn = D;
+    } else if (leg == 0) {
+        const int D = DL;
+        g.M = g.N = D;
+        g.Kin = DR * DP;
+        g.sam = 1;
+        g.sak = DL;
+        g.sbk = DL;
+        g.sbn = 1;
+        g.c_plane = (int64_t)D * D;
+        g.scn = D;
+    } else {
+        const int D = DR;
+        g.M = g.N = D;
+        g.Kin = DL;
+        g.Kout = DP;
+        g.sam = DL;
+        g.sak = 1;
+        g.sako = (int64_t)DL * DR;
+        g.sbk = 1;
+        g.sbko = (int64_t)DL * DR;
+        g.sbn = DL;
+        g.c_plane = (int64_t)D * D;
+        g.scn = D;
+    }
+    c.run(g);
+}
+
+// A stack: out slot i = sum_j V[i][j] N_j for the operator stack Nstk (slots
+// 1..ns of a [H, N_1..] stack with matrices D x D), V given as a planar
+// (ni x ns) matrix in column-major j + ns*i (i.e. V^T col-major).
+void vsum_stack(Ctx<double>& c, const double* Nstk, int D, int ns, const double* Vt, int ni,
+                double* out_slot1) {
+    if (ni <= 0 || ns <= 0) return;
+    const int64_t D2 = (int64_t)D * D;
+    Gemm<double> g;
+    g.skip = c.skip;
+    g.M = (int)D2;
+    g.N = ni;
+    g.Kin = ns;
+    g.A = Nstk + 2 * D2;   // slot 1
+    g.a_plane = D2;
+    g.sam = 1;
+    g.sak = 2 * D2;
+    g.B = Vt;
+    g.b_plane = (int64_t)ns * ni;
+    g.sbk = 1;
+    g.sbn = ns;
+    g.C = out_slot1;
+    g.c_plane = D2;
+    g.scm = 1;
+    g.scn = 2 * D2;
+    c.run(g);
+}
+
+// ---------------------------------------------------------------------------
+// environments and effective Hamiltonians
+// ---------------------------------------------------------------------------
+const double* child_block(ttn_handle* h, int v, int side) {
+    if (is_bottom(h, v)) {
+        const int leaf = 2 * h->idx[v] + side;
+        return h->leafblk + (int64_t)leaf * 4 * h->d * h->d;
+    }
+    return h->up[side == 0 ? h->ch0[v] : h->ch1[v]];
+}
+
+// Operator description of H_eff at node v (or K_eff at the link above v).
+struct OpDesc {
+    int DL, DR, DP, sL, sR;
+    const double* Lb;   // [H_L, N_i (i in S_L)]      DL x DL each
+    const double* Rb;   // [H_R, N_j (j in S_R)]      DR x DR
+    const double* Bb;   // [H_R, A_i (i in S_L)]      DR x DR, A_i = sum_j V_ij N_j
+    const double* Wb;   // [H_P, W_i (S_L), W_j (S_R)] DP x DP, nullptr at the root
+};
+
+// Bstk = [H_R, A_1..A_sL] for node v
+void prepare_B(ttn_handle* h, Ctx<double>& c, int v, const double* Rb, int DR, int sL, int sR) {
+    const int64_t D2 = (int64_t)DR * DR;
+    copy_d(Rb, h->Bstk, 2 * D2, c.skip, h->stream);
+    vsum_stack(c, Rb, DR, sR, h->vRL[v], sL, h->Bstk + 2 * D2);
+}
+
+OpDesc node_op(ttn_handle* h, Ctx<double>& c, int v) {
+    OpDesc o;
+    o.DL = h->DL[v];
+    o.DR = h->DR[v];
+    o.DP = h->DP[v];
+    o.sL = o.sR = sites_left(h, v);
+    o.Lb = child_block(h, v, 0);
+    o.Rb = child_block(h, v, 1);
+    prepare_B(h, c, v, o.Rb, o.DR, o.sL, o.sR);
+    o.Bb = h->Bstk;
+    o.Wb = v == h->root ? nullptr : h->dn[v];
+    return o;
+}
+
+// K_eff on the link above v as an operator on a (D_below, 1, D_above) tensor
+OpDesc bond_op(ttn_handle* h, int v) {
+    OpDesc o;
+    o.DL = h->DP[v];
+    o.DR = 1;
+    o.DP = h->DP[v];
+    o.sL = h->scount[v];
+    o.sR = 0;
+    o.Lb = h->up[v];
+    o.Rb = nullptr;
+    o.Bb = nullptr;
+    o.Wb = h->dn[v];
+    return o;
+}
+
+// Y = H X with X in slot 0 of the stack Xs (slot stride 2n).
+template <typename R>
+void apply_op(Ctx<R>& c, const OpDesc& o, const R* Lb, const R* Rb, const R* Bb, const R* Wb, R* Xs,
+              R* Y) {
+    const int DL = o.DL, DR = o.DR, DP = o.DP, sL = o.sL, sR = o.sR;
+    const int64_t n = (int64_t)DL * DR * DP, sx = 2 * n;
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
+    // stage A: Y = H_L X, U_i = N_i X on the left leg
+    leg_apply<R>(c, 0, Lb, 0, Xs, 0, Y, 0, DL, DR, DP, 1, 0);
+    if (sL > 0) leg_apply<R>(c, 0, Lb + 2 * L2, 2 * L2, Xs, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
+    // stage B: Z_j = N_j X on the right leg (needed by the parent-leg terms)
+    if (Wb && sR > 0) leg_apply<R>(c, 1, Rb + 2 * R2, 2 * R2, Xs, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
+    // stage C: Y += H_R X + sum_i A_i U_i on the right leg
+    if (Bb) leg_apply_sum<R>(c, 1, Bb, 2 * R2, Xs, sx, Y, DL, DR, DP, 1 + sL, 1);
+    // stage D: Y += H_P X + sum_i W_i U_i + sum_j W_j Z_j on the parent leg
+    if (Wb) leg_apply_sum<R>(c, 2, Wb, 2 * P2, Xs, sx, Y, DL, DR, DP, 1 + sL + sR, 1);
+}
+
+// FP32 copies of an operator's stacks for the mixed-precision matvec
+void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
+    const int64_t L2 = (int64_t)o.DL * o.DL, R2 = (int64_t)o.DR * o.DR, P2 = (int64_t)o.DP * o.DP;
+    chk(h, o.Lb, 2 * (1 + o.sL) * L2, "L stack");
+    chk(h, h->Lf, (1 + o.sL) * L2, "L stack fp32");
+    if (o.Rb) chk(h, o.Rb, 2 * (1 + o.sR) * R2, "R stack");
+    if (o.Bb) chk(h, o.Bb, 2 * (1 + o.sL) * R2, "B stack");
+    if (o.Wb) {
+        chk(h, o.Wb, 2 * (1 + o.sL + o.sR) * P2, "W stack");
+        chk(h, h->Wf, (1 + o.sL + o.sR) * P2, "W stack fp32");
+    }
+    convert_d2f(o.Lb, h->Lf, 2 * (1 + o.sL) * L2, skip, h->stream);
+    if (o.Rb) convert_d2f(o.Rb, h->Rf, 2 * (1 + o.sR) * R2, skip, h->stream);
+    if (o.Bb) convert_d2f(o.Bb, h->Bf, 2 * (1 + o.sL) * R2, skip, h->stream);
+    if (o.Wb) convert_d2f(o.Wb, h->Wf, 2 * (1 + o.sL + o.sR) * P2, skip, h->stream);
+}
+
+void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, const int* skip,
+                   bool force_fp64 = false) {
+    const int64_t n = (int64_t)o.DL * o.DR * o.DP;
+    if (h->prec == TTN_PREC_FP32 && !force_fp64) {
+        Ctx<float> c{h, skip};
+        convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
+        apply_op<float>(c, o, h->Lf, o.Rb ? h->Rf : nullptr, o.Bb ? h->Bf : nullptr,
+                        o.Wb ? h->Wf : nullptr, h->Xf, h->Yf);
+        convert_f2d(h->Yf, y, 2 * n, skip, h->stream);
+    } else {
+        Ctx<double> c{h, skip};
+        copy_d(x, h->X, 2 * n, skip, h->stream);
+        apply_op<double>(c, o, o.Lb, o.Rb, o.Bb, o.Wb, h->X, y);
+    }
+}
+
+// x <- exp(-i tau Op) x by Lanczos (full re-orthogonalisation, device scalars)
+void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
+    const int64_t n = (int64_t)o.DL * o.DR * o.DP;
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, (n + 255) / 256);
+    hipStream_t s = h->stream;
+    LanczosDev* lz = h->lz;
+    chk(h, x, 2 * n, "krylov input");
+    chk(h, h->Vk, 2 * n * (h->m + 1), "krylov basis");
+    chk(h, h->W, 2 * n, "krylov work vector");
+    chk(h, h->X, 2 * n, "stack slot 0");
+    if (h->prec == TTN_PREC_FP32) {
+        chk(h, h->Xf, n, "fp32 stack slot 0");
+        chk(h, h->Yf, n, "fp32 output");
+        stage_f32(h, o, nullptr);
+    }
+    lz_start(x, n, h->Vk, lz, h->red, nb, s);
+    for (int j = 0; j < h->m; ++j) {
+        double* vj = h->Vk + 2 * n * j;
+        apply_op_prec(h, o, vj, h->W, &lz->done);
+        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s);
+        if (j == h->m - 1) break;
+        lz_subtract(h->Vk, j + 1, h->W, n, lz, s);
+        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, -1, s);
+        lz_subtract(h->Vk, j + 1, h->W, n, lz, s);
+        lz_next(h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s);
+    }
+    lz_expm(lz, tau, h->st, s);
+    lz_combine(h->Vk, n, x, lz, s);
+}
+
+// ---------------------------------------------------------------------------
+// QR gauge move (CholeskyQR2): T[.., a, ..] = sum_k Q[.., k, ..] R[k, a]
+// with R upper triangular, real positive diagonal; Q overwrites T, R -> Rout.
+// ---------------------------------------------------------------------------
+void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, double* Rout) {
+    Ctx<double> c{h, nullptr};
+    const int D = leg == 0 ? DL : (leg == 1 ? DR : DP);
+    const int64_t n = (int64_t)DL * DR * DP;
+    chk(h, Tv, 2 * n, "qr tensor");
+    chk(h, h->Qtmp, 2 * n, "qr scratch");
+    chk(h, h->G, 2 * (int64_t)D * D, "gram");
+    chk(h, h->Linv, 2 * (int64_t)D * D, "Linv");
+    chk(h, h->R1, 2 * (int64_t)D * D, "R1");
+    chk(h, Rout, 2 * (int64_t)D * D, "R out");
+    if (D > 128) chk(h, h->cholwork, (int64_t)D * (D + 1), "cholesky work");
+    leg_gram(c, leg, Tv, Tv, 0, h->G, 0, DL, DR, DP, 1);
+    chol_inv(h->G, D, h->Linv, h->R1, nullptr, h->cholwork, h->st, h->stream);
+    leg_apply<double>(c, leg, h->Linv, 0, Tv, 0, h->Qtmp, 0, DL, DR, DP, 1, 0, true, false);
+    leg_gram(c, leg, h->Qtmp, h->Qtmp, 0, h->G, 0, DL, DR, DP, 1);
+    chol_inv(h->G, D, h->Linv, Rout, h->R1, h->cholwork, h->st, h->stream);
+    leg_apply<double>(c, leg, h->Linv, 0, h->Qtmp, 0, Tv, 0, DL, DR, DP, 1, 0, true, false);
+    (void)n;
+}
+
+// T (tensor of node v) <- Op on leg (via a temporary)
+void absorb(ttn_handle* h, int v, int leg, const double* Op, bool trans) {
+    Ctx<double> c{h, nullptr};
+    const int64_t n = nsize(h, v);
+    chk(h, h->Ttmp, 2 * n, "absorb scratch");
+    leg_apply<double>(c, leg, Op, 0, h->T[v], 0, h->Ttmp, 0, h->DL[v], h->DR[v], h->DP[v], 1, 0, false,
+                      trans);
+    copy_d(h->Ttmp, h->T[v], 2 * n, nullptr, h->stream);
+}
+
+void build_up(ttn_handle* h, int v) {
+    Ctx<double> c{h, nullptr};
+    const int DL = h->DL[v], DR = h->DR[v], DP = h->DP[v];
+    const int sL = sites_left(h, v), sR = sL;
+    const int64_t n = nsize(h, v), sx = 2 * n;
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
+    const double* Q = h->T[v];
+    const double* Lb = child_block(h, v, 0);
+    const double* Rb = child_block(h, v, 1);
+    prepare_B(h, c, v, Rb, DR, sL, sR);
+    double* Xs = h->X;
+    double* Y = h->W;
+    leg_apply<double>(c, 0, Lb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
+    leg_apply<double>(c, 0, Lb + 2 * L2, 2 * L2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
+    leg_apply<double>(c, 1, Rb + 2 * R2, 2 * R2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
+    leg_apply<double>(c, 1, h->Bstk, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
+    leg_apply_sum<double>(c, 1, h->Bstk + 2 * R2, 2 * R2, Xs + sx, sx, Y, DL, DR, DP, sL, 1);
+    double* E = h->up[v];
+    leg_gram(c, 2, Q, Y, 0, E, 0, DL, DR, DP, 1);
+    leg_gram(c, 2, Q, Xs + sx, sx, E + 2 * P2, 2 * P2, DL, DR, DP, sL + sR);
+}
+
+// down environment of the link above c, from its parent u canonical toward c
+void build_down(ttn_handle* h, int cnode) {
+    Ctx<double> c{h, nullptr};
+    const int u = h->parent[cnode];
+    const int leg = leg_in_parent(h, cnode);
+    const int DL = h->DL[u], DR = h->DR[u], DP = h->DP[u];
+    const int sL = sites_left(h, u), sR = sL;
+    const int64_t n = nsize(h, u), sx = 2 * n;
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
+    const double* Q = h->T[u];
+    const double* Lb = child_block(h, u, 0);
+    const double* Rb = child_block(h, u, 1);
+    const double* Wb = u == h->root ? nullptr : h->dn[u];
+    double* Xs = h->X;
+    double* Y = h->W;
+    double* E = h->dn[cnode];
+    const int Dc = leg == 0 ? DL : DR;
+    const int64_t C2 = (int64_t)Dc * Dc;
+    if (leg == 0) {
+        // block: H_R + H_P + sum_{j in R} N_j W_j ; fields W_i (i in L): A_i on R + W_i on P
+        leg_apply<double>(c, 1, Rb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
+        if (Wb) {
+            leg_apply<double>(c, 2, Wb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
+            leg_apply<double>(c, 1, Rb + 2 * R2, 2 * R2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
+            leg_apply_sum<double>(c, 2, Wb + 2 * P2 * (1 + sL), 2 * P2, Xs + sx * (1 + sL), sx, Y, DL, DR,
+                                  DP, sR, 1);
+        }
+        leg_gram(c, 0, Q, Y, 0, E, 0, DL, DR, DP, 1);
+        prepare_B(h, c, u, Rb, DR, sL, sR);   // A_i = sum_{j in R} V_ij N_j
+        leg_apply<double>(c, 1, h->Bstk + 2 * R2, 2 * R2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
+        if (Wb) leg_apply<double>(c, 2, Wb + 2 * P2, 2 * P2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 1);
+        leg_gram(c, 0, Q, Xs + sx, sx, E + 2 * C2, 2 * C2, DL, DR, DP, sL);
+    } else {
+        leg_apply<double>(c, 0, Lb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
+        if (Wb) {
+            leg_apply<double>(c, 2, Wb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
+            leg_apply<double>(c, 0, Lb + 2 * L2, 2 * L2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
+            leg_apply_sum<double>(c, 2, Wb + 2 * P2, 2 * P2, Xs + sx, sx, Y, DL, DR, DP, sL, 1);
+        }
+        leg_gram(c, 1, Q, Y, 0, E, 0, DL, DR, DP, 1);
+        // A''_j = sum_{k in L} V_jk N_k (left operators), j in R
+        vsum_stack(c, Lb, DL, sL, h->vLR[u], sR, h->Astk + 2 * L2);
+        leg_apply<double>(c, 0, h->Astk + 2 * L2, 2 * L2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
+        if (Wb)
+            leg_apply<double>(c, 2, Wb + 2 * P2 * (1 + sL), 2 * P2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR,
+                              DP, sR, 1);
+        leg_gram(c, 1, Q, Xs + sx * (1 + sL), sx, E + 2 * C2, 2 * C2, DL, DR, DP, sR);
+    }
+}
+
+void evolve_node(ttn_handle* h, int v, double tau) {
+    Ctx<double> c{h, nullptr};
+    OpDesc o = node_op(h, c, v);
+    lanczos_expm(h, o, h->T[v], tau);
+}
+
+void evolve_bond(ttn_handle* h, int v, double* C, double tau) {
+    OpDesc o = bond_op(h, v);
+    lanczos_expm(h, o, C, -tau);
+}
+
+// ---------------------------------------------------------------------------
+// sweeps
+// ---------------------------------------------------------------------------
+void visit_fwd(ttn_handle* h, int v, double tau) {
+    const int u = h->parent[v], leg = leg_in_parent(h, v);
+    qr_toward(h, h->DL[u], h->DR[u], h->DP[u], h->T[u], leg, h->Rq);
+    absorb(h, v, 2, h->Rq, false);                 // T_v[.., k] = sum_a R[k, a] T_v[.., a]
+    build_down(h, v);
+    if (!is_bottom(h, v)) {
+        visit_fwd(h, h->ch0[v], tau);
+        visit_fwd(h, h->ch1[v], tau);
+    }
+    evolve_node(h, v, tau);
+    qr_toward(h, h->DL[v], h->DR[v], h->DP[v], h->T[v], 2, h->Cb);
+    build_up(h, v);
+    evolve_bond(h, v, h->Cb, tau);
+    absorb(h, u, leg, h->Cb, false);               // T_u[k at leg] = sum_p C[k, p] T_u[p at leg]
+}
+
+void visit_bwd(ttn_handle* h, int v, double tau) {
+    const int u = h->parent[v], leg = leg_in_parent(h, v);
+    const int D = h->DP[v];
+    chk(h, h->Cb, 2 * (int64_t)D * D, "bond buffer");
+    qr_toward(h, h->DL[u], h->DR[u], h->DP[u], h->T[u], leg, h->Rq);
+    build_down(h, v);
+    transpose_c(h->Rq, h->Cb, D, D, h->stream);    // C[below, above] = R^T
+    evolve_bond(h, v, h->Cb, tau);
+    absorb(h, v, 2, h->Cb, true);                  // T_v[.., k] = sum_a T_v[.., a] C[a, k]
+    evolve_node(h, v, tau);
+    if (!is_bottom(h, v)) {
+        visit_bwd(h, h->ch1[v], tau);
+        visit_bwd(h, h->ch0[v], tau);
+    }
+    qr_toward(h, h->DL[v], h->DR[v], h->DP[v], h->T[v], 2, h->Rq);
+    build_up(h, v);
+    absorb(h, u, leg, h->Rq, false);
+}
+
+void sweep_fwd(ttn_handle* h, double tau) {
+    if (!is_bottom(h, h->root)) {
+        visit_fwd(h, h->ch0[h->root], tau);
+        visit_fwd(h, h->ch1[h->root], tau);
+    }
+    evolve_node(h, h->root, tau);
+}
+
+void sweep_bwd(ttn_handle* h, double tau) {
+    evolve_node(h, h->root, tau);
+    if (!is_bottom(h, h->root)) {
+        visit_bwd(h, h->ch1[h->root], tau);
+        visit_bwd(h, h->ch0[h->root], tau);
+    }
+}
+
+void postorder(const ttn_handle* h, int v, std::vector<int>& out) {
+    if (!is_bottom(h, v)) {
+        postorder(h, h->ch0[v], out);
+        postorder(h, h->ch1[v], out);
+    }
+    out.push_back(v);
+}
+
+int segment_at(const ttn_handle* h, double t) {
+    for (int s = 0; s < h->n_seg; ++s)
+        if (h->edges[s] <= t && t < h->edges[s + 1]) return s;
+    return -1;
+}
+
+__global__ void k_leaf_blocks_seg(double* blk, const int* leaf_site, const double* om,
+                                  const double* de, int n_seg, int seg, int n_leaves, int d,
+                                  double leak) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_leaves) return;
+    const int s = leaf_site[k];
+    const int dd = d * d;
+    double* hh = blk + (int64_t)k * 4 * dd;
+    double* nn = hh + 2 * dd;
+    for (int e = 0; e < 2 * dd; ++e) {
+        hh[e] = 0.0;
+        nn[e] = 0.0;
+    }
+    const double o2 = seg >= 0 ? 0.5 * om[(int64_t)s * n_seg + seg] : 0.0;
+    const double dl = seg >= 0 ? de[(int64_t)s * n_seg + seg] : 0.0;
+    hh[1 + d * 2] += o2;   // Omega/2 (|1><r| + |r><1|), r = level 2
+    hh[2 + d * 1] += o2;
+    if (d >= 4) {           // leak_ratio Omega/2 (|leak><r| + h.c.), leak = level 3
+        hh[3 + d * 2] += leak * o2;
+        hh[2 + d * 3] += leak * o2;
+    }
+    hh[2 + d * 2] -= dl;   // -Delta |r><r|
+    nn[2 + d * 2] = 1.0;
+}
+
+void set_hamiltonian(ttn_handle* h, int seg) {
+    h->cur_seg = seg;
+    if (h->dry) return;
+    hipLaunchKernelGGL(k_leaf_blocks_seg, dim3((h->N + 63) / 64), dim3(64), 0, h->stream, h->leafblk,
+                       h->d_leaf_site, h->d_omega, h->d_delta, h->n_seg, seg, h->N, h->d, h->leak);
+    h->cur_seg = seg;
+}
+
+void rebuild_up(ttn_handle* h) {
+    std::vector<int> po;
+    postorder(h, h->root, po);
+    for (int v : po)
+        if (v != h->root) build_up(h, v);
+}
+
+void apply_events_at(ttn_handle* h, int64_t step) {
+    for (auto& e : h->events) {
+        if (e.step != step || e.applied) continue;
+        e.applied = true;
+        int k = 0;
+        while (h->leaf_site[k] != e.site) ++k;
+        const int b = k / 2, side = k & 1;
+        absorb(h, b, side, e.U, false);
+    }
+}
+
+void canonicalise(ttn_handle* h) {
+    std::vector<int> po;
+    postorder(h, h->root, po);
+    for (int v : po) {
+        if (v == h->root) break;
+        qr_toward(h, h->DL[v], h->DR[v], h->DP[v], h->T[v], 2, h->Rq);
+        absorb(h, h->parent[v], leg_in_parent(h, v), h->Rq, false);
+    }
+    const int r = h->root;
+    const int64_t n = nsize(h, r);
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, (n + 255) / 256);
+    lz_start(h->T[r], n, h->T[r], h->lz_obs, h->red, nb, h->stream);
+}
+
+void reset_step_dev(ttn_handle* h) {
+    StepDev& s = h->h_stepinit;
+    s = StepDev{};
+    s.bad = 0;
+    s.min_krylov = 1 << 30;
+    const double big = 1e308;
+    std::memcpy(&s.min_rdiag_bits, &big, sizeof(double));
+    h2d(h, h->st, &s, sizeof(s));
+}
+
+// <x|y> into *out (complex) using the observation Lanczos scratch
+void dot_c(ttn_handle* h, const double* x, const double* y, int64_t n, double out[2]) {
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, (n + 255) / 256);
+    chk(h, x, 2 * n, "dot x");
+    chk(h, y, 2 * n, "dot y");
+    h2d(h, h->lz_obs, &h->h_lzinit, sizeof(LanczosDev));
+    lz_project(x, 1, y, n, h->red, nb, h->lz_obs, -1, h->stream);
+    d2h(h, &h->h_lzout, h->lz_obs, sizeof(LanczosDev));
+    sync(h);
+    out[0] = h->h_lzout.c[0];
+    out[1] = h->h_lzout.c[1];
+}
+
+// ||psi||^2 and <psi|H|psi> with the centre at the root (FP64 matvec)
+void observables(ttn_handle* h, double* norm2, double* energy) {
+    const int r = h->root;
+    const int64_t n = nsize(h, r);
+    Ctx<double> c{h, nullptr};
+    OpDesc o = node_op(h, c, r);
+    apply_op_prec(h, o, h->T[r], h->W, nullptr, true);
+    double a[2], b[2];
+    dot_c(h, h->T[r], h->T[r], n, a);
+    dot_c(h, h->T[r], h->W, n, b);
+    *norm2 = a[0];
+    *energy = b[0];
+}
+
+// product-state overlap <phi|psi>, phi given per leaf (planar d-vectors, already conjugated)
+void product_overlap(ttn_handle* h, const std::vector<double>& leafvec, double out[2]) {
+    chk(h, h->ov_leaf, (int64_t)leafvec.size(), "leaf vectors");
+    h2d(h, h->ov_leaf, leafvec.data(), leafvec.size() * sizeof(double));
+    std::vector<int64_t> voff(h->n_nodes);
+    int64_t o = 0;
+    for (int v = 0; v < h->n_nodes; ++v) {
+        voff[v] = o;
+        o += 2 * h->DP[v];
+    }
+    for (int v = 0; v < h->n_nodes; ++v) {
+        const double *a, *b;
+        if (is_bottom(h, v)) {
+            a = h->ov_leaf + (int64_t)2 * h->d * (2 * h->idx[v]);
+            b = h->ov_leaf + (int64_t)2 * h->d * (2 * h->idx[v] + 1);
+        } else {
+            a = h->ov_vec + voff[h->ch0[v]];
+            b = h->ov_vec + voff[h->ch1[v]];
+        }
+        chk(h, a, 2 * h->DL[v], "overlap a");
+        chk(h, b, 2 * h->DR[v], "overlap b");
+        chk(h, h->ov_vec + voff[v], 2 * h->DP[v], "overlap out");
+        contract_node_vec(h->T[v], h->DL[v], h->DR[v], h->DP[v], a, b, h->ov_vec + voff[v], h->stream);
+    }
+    double res[2];
+    d2h(h, res, h->ov_vec + voff[h->root], 2 * sizeof(double));
+    sync(h);
+    out[0] = res[0];
+    out[1] = res[1];
+}
+
+// <a|b> by bottom-up contraction; node `mod` of b optionally replaced by modT
+void ttn_contract(ttn_handle* a, ttn_handle* b, int mod, const double* modT, double out[2]) {
+    ttn_handle* h = a;
+    Ctx<double> c{h, nullptr};
+    const int64_t Dm2 = (int64_t)h->Dmax * h->Dmax;
+    for (int v = 0; v < h->n_nodes; ++v) {
+        const int DL = h->DL[v], DR = h->DR[v], DP = h->DP[v];
+        const double* TB = (v == mod) ? modT : b->T[v];
+        double* M = h->ov_M + 2 * Dm2 * v;
+        if (is_bottom(h, v)) {
+            leg_gram(c, 2, a->T[v], TB, 0, M, 0, DL, DR, DP, 1);
+        } else {
+            const double* ML = h->ov_M + 2 * Dm2 * h->ch0[v];
+            const double* MR = h->ov_M + 2 * Dm2 * h->ch1[v];
+            leg_apply<double>(c, 0, ML, 0, TB, 0, h->ov_Y1, 0, DL, DR, DP, 1, 0);
+            leg_apply<double>(c, 1, MR, 0, h->ov_Y1, 0, h->ov_Y2, 0, DL, DR, DP, 1, 0);
+            leg_gram(c, 2, a->T[v], h->ov_Y2, 0, M, 0, DL, DR, DP, 1);
+        }
+    }
+    double res[2];
+    const double* Mr = h->ov_M + 2 * Dm2 * h->root;
+    d2h(h, &res[0], Mr, sizeof(double));
+    d2h(h, &res[1], Mr + 1, sizeof(double));
+    sync(h);
+    out[0] = res[0];
+    out[1] = res[1];
+}
+
+// host-side initial isometries (product state, Gram-Schmidt completion, dressing)
+void initial_tensors(ttn_handle* h, const ttn_config* cfg) {
+    int64_t noff = 0;
+    for (int v = 0; v < h->n_nodes; ++v) {
+        const int DL = h->DL[v], DR = h->DR[v], DP = h->DP[v];
+        const int64_t LR = (int64_t)DL * DR, n = LR * DP;
+        std::vector<double> re(n, 0.0), im(n, 0.0);
+        std::vector<std::vector<double>> cr, ci;   // accepted columns
+        std::vector<double> c0r(LR, 0.0), c0i(LR, 0.0);
+        if (is_bottom(h, v)) {
+            const int a = h->leaf_site[2 * h->idx[v]], b = h->leaf_site[2 * h->idx[v] + 1];
+            const double* pa = cfg->init_product + 2 * h->d * a;
+            const double* pb = cfg->init_product + 2 * h->d * b;
+            for (int r = 0; r < DR; ++r)
+                for (int l = 0; l < DL; ++l) {
+                    c0r[l + DL * r] = pa[2 * l] * pb[2 * r] - pa[2 * l + 1] * pb[2 * r + 1];
+                    c0i[l + DL * r] = pa[2 * l] * pb[2 * r + 1] + pa[2 * l + 1] * pb[2 * r];
+                }
+        } else {
+            c0r[0] = 1.0;
+        }
+        cr.push_back(c0r);
+        ci.push_back(c0i);
+        for (int64_t k = 0; k < LR && (int)cr.size() < DP; ++k) {
+            std::vector<double> er(LR, 0.0), ei(LR, 0.0);
+            er[k] = 1.0;
+            for (size_t q = 0; q < cr.size(); ++q) {
+                double dr = 0, di = 0;   // <c_q, e>
+                for (int64_t i = 0; i < LR; ++i) {
+                    dr += cr[q][i] * er[i] + ci[q][i] * ei[i];
+                    di += cr[q][i] * ei[i] - ci[q][i] * er[i];
+                }
+                for (int64_t i = 0; i < LR; ++i) {
+                    er[i] -= dr * cr[q][i] - di * ci[q][i];
+                    ei[i] -= dr * ci[q][i] + di * cr[q][i];
+                }
+            }
+            double nrm = 0;
+            for (int64_t i = 0; i < LR; ++i) nrm += er[i] * er[i] + ei[i] * ei[i];
+            nrm = std::sqrt(nrm);
+            if (nrm > COMPLETION_TOL) {
+                for (int64_t i = 0; i < LR; ++i) {
+                    er[i] /= nrm;
+                    ei[i] /= nrm;
+                }
+                cr.push_back(er);
+                ci.push_back(ei);
+            }
+        }
+        if ((int)cr.size() != DP) throw StatusError{TTN_EINVAL, "isometry completion failed"};
+        for (int p = 0; p < DP; ++p)
+            for (int64_t i = 0; i < LR; ++i) {
+                re[i + LR * p] = cr[p][i];
+                im[i + LR * p] = ci[p][i];
+            }
+        if (cfg->dress_eps > 0) {
+            if (!cfg->dress_noise || noff + n > cfg->dress_noise_len)
+                throw StatusError{TTN_EINVAL, "dressing noise stream too short"};
+            const double sc = cfg->dress_eps / std::sqrt((double)LR);
+            for (int64_t i = 0; i < n; ++i) {
+                re[i] += sc * cfg->dress_noise[2 * (noff + i)];
+                im[i] += sc * cfg->dress_noise[2 * (noff + i) + 1];
+            }
+        }
+        noff += n;
+        h2d(h, h->T[v], re.data(), n * sizeof(double));
+        h2d(h, h->T[v] + n, im.data(), n * sizeof(double));
+        sync(h);
+    }
+}
+
+void validate(const ttn_config* c) {
+    if (!c) throw StatusError{TTN_EINVAL, "null config"};
+    if (c->n_sites < 2 || c->n_sites > 1024 || (c->n_sites & (c->n_sites - 1)))
+        throw StatusError{TTN_EINVAL, "n_sites must be a power of two in [2, 1024]"};
+    if (c->d < 3 || c->d > 4) throw StatusError{TTN_EINVAL, "d must be 3 or 4"};
+    if (c->chi < 1 || c->chi > 256) throw StatusError{TTN_EINVAL, "chi must be in [1, 256]"};
+    if (c->krylov_dim < 1 || c->krylov_dim > KRYLOV_MAX)
+        throw StatusError{TTN_EINVAL, "krylov_dim must be in [1, 16]"};
+    if (c->precision != TTN_PREC_FP64 && c->precision != TTN_PREC_FP32)
+        throw StatusError{TTN_EINVAL, "unknown precision"};
+    if (!c->pos_xy || !c->leaf_order || !c->init_product)
+        throw StatusError{TTN_EINVAL, "missing positions, leaf order or initial product state"};
+    std::vector<char> seen(c->n_sites, 0);
+    for (int k = 0; k < c->n_sites; ++k) {
+        const int s = c->leaf_order[k];
+        if (s < 0 || s >= c->n_sites || seen[s]) throw StatusError{TTN_EINVAL, "leaf order is not a permutation"};
+        seen[s] = 1;
+    }
+    if (!(c->dress_eps >= 0) || !std::isfinite(c->c6) || !std::isfinite(c->leak_ratio))
+        throw StatusError{TTN_EINVAL, "bad scalar parameter"};
+    for (int i = 0; i < c->n_sites; ++i)
+        for (int j = 0; j < i; ++j)
+            if (c->pos_xy[2 * i] == c->pos_xy[2 * j] && c->pos_xy[2 * i + 1] == c->pos_xy[2 * j + 1])
+                throw StatusError{TTN_EINVAL, "two sites share a position"};
+}
+
+void setup_config(ttn_handle* h, const ttn_config* c) {
+    h->N = c->n_sites;
+    h->d = c->d;
+    h->chi = c->chi;
+    h->m = c->krylov_dim;
+    h->prec = c->precision;
+    h->c6 = c->c6;
+    h->rcut = c->r_cut;
+    h->leak = c->leak_ratio;
+    h->leaf_site.assign(c->leaf_order, c->leaf_order + c->n_sites);
+    build_tree(h);
+}
+
+// van der Waals couplings V_ij = C6 / d_ij^6 (Eq. c6, positive, i != j, cutoff)
+void build_couplings(ttn_handle* h, const double* pos) {
+    h->V.assign((size_t)h->N * h->N, 0.0);
+    for (int i = 0; i < h->N; ++i)
+        for (int j = 0; j < h->N; ++j) {
+            if (i == j) continue;
+            const double dx = pos[2 * i] - pos[2 * j], dy = pos[2 * i + 1] - pos[2 * j + 1];
+            const double dist = std::sqrt(dx * dx + dy * dy);
+            if (h->rcut > 0 && dist > h->rcut) continue;
+            h->V[(size_t)i * h->N + j] = h->c6 / std::pow(dist, 6);
+        }
+    for (int v = 0; v < h->n_nodes; ++v) {
+        const int sL = sites_left(h, v), f = h->sfirst[v];
+        std::vector<double> lr(2 * (size_t)sL * sL, 0.0), rl(2 * (size_t)sL * sL, 0.0);
+        for (int i = 0; i < sL; ++i)
+            for (int j = 0; j < sL; ++j) {
+                const int si = h->leaf_site[f + i], sj = h->leaf_site[f + sL + j];
+                const double val = h->V[(size_t)si * h->N + sj];
+                lr[i + (size_t)sL * j] = val;   // V[i in L][j in R], column-major i + sL j
+                rl[j + (size_t)sL * i] = val;   // V[j in R][i in L] transposed layout
+            }
+        h2d(h, h->vLR[v], lr.data(), lr.size() * sizeof(double));
+        h2d(h, h->vRL[v], rl.data(), rl.size() * sizeof(double));
+        sync(h);
+    }
+}
+
+thread_local std::string g_init_error;
+
+int fail(ttn_handle* h, const StatusError& e) {
+    if (h) {
+        h->err = e.msg;
+        if (e.code == TTN_ENUMERIC || e.code == TTN_EDEVICE) h->poisoned = true;
+    }
+    return e.code;
+}
+
+void check_step_flags(ttn_handle* h, StepDev* out) {
+    StepDev& s = h->h_stepout;
+    d2h(h, &s, h->st, sizeof(s));
+    sync(h);
+    if (h->dry) {
+        s.min_krylov = h->m;
+        const double one = 1.0;
+        std::memcpy(&s.min_rdiag_bits, &one, sizeof(double));
+    }
+    if (out) *out = s;
+    if (s.bad) throw StatusError{TTN_ENUMERIC, "non-positive pivot in a QR gauge move (rank-deficient node)"};
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int ttn_workspace_query(const ttn_config* cfg, size_t* device_bytes) {
+    try {
+        validate(cfg);
+        if (!device_bytes) return TTN_EINVAL;
+        ttn_handle h;
+        setup_config(&h, cfg);
+        Bump b(nullptr, 0);
+        plan(&h, b);
+        *device_bytes = b.off + 256;
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return e.code;
+    } catch (...) {
+        return TTN_EINVAL;
+    }
+}
+
+int ttn_init(const ttn_config* cfg, void* d_workspace, size_t bytes, void* hip_stream, ttn_handle** out) {
+    if (!out) return TTN_EINVAL;
+    *out = nullptr;
+    ttn_handle* h = nullptr;
+    try {
+        validate(cfg);
+        if (!d_workspace) return TTN_EINVAL;
+        h = new ttn_handle();
+        h->stream = (hipStream_t)hip_stream;
+        setup_config(h, cfg);
+        Bump b(d_workspace, bytes, &h->regions);
+        plan(h, b);
+        sort_regions(h);
+        h->ws_bytes = bytes;
+        h2d(h, h->d_leaf_site, h->leaf_site.data(), h->N * sizeof(int));
+        build_couplings(h, cfg->pos_xy);
+        initial_tensors(h, cfg);
+        reset_step_dev(h);
+        if (!h->dry) HIPCHECK(hipGetLastError());
+        canonicalise(h);
+        if (!h->dry) HIPCHECK(hipGetLastError());
+        StepDev s;
+        check_step_flags(h, &s);
+        *out = h;
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        g_init_error = e.msg;
+        delete h;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_init_error = "host allocation failed";
+        delete h;
+        return TTN_ENOMEM;
+    } catch (...) {
+        g_init_error = "unexpected exception";
+        delete h;
+        return TTN_EINVAL;
+    }
+}
+
+int ttn_set_pulses(ttn_handle* h, int32_t n_seg, const double* seg_edges, const double* omega,
+                   const double* delta, int32_t n_events, const int32_t* ev_step, const int32_t* ev_site,
+                   const double* ev_u) {
+    if (!h) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (n_seg < 0 || (n_seg > 0 && (!seg_edges || !omega || !delta)) || n_events < 0 ||
+            (n_events > 0 && (!ev_step || !ev_site || !ev_u)))
+            throw StatusError{TTN_EINVAL, "bad pulse arguments"};
+        for (int s = 0; s < n_seg; ++s)
+            if (!(seg_edges[s + 1] > seg_edges[s])) throw StatusError{TTN_EINVAL, "segment edges must ascend"};
+        for (int64_t i = 0; i < (int64_t)h->N * n_seg; ++i)
+            if (!std::isfinite(omega[i]) || !std::isfinite(delta[i]))
+                throw StatusError{TTN_EINVAL, "non-finite pulse value"};
+        for (int e = 0; e < n_events; ++e) {
+            if (ev_site[e] < 0 || ev_site[e] >= h->N || ev_step[e] < 0)
+                throw StatusError{TTN_EINVAL, "bad gate event"};
+            for (int k = 0; k < 2 * h->d * h->d; ++k)
+                if (!std::isfinite(ev_u[(int64_t)e * 2 * h->d * h->d + k]))
+                    throw StatusError{TTN_EINVAL, "non-finite gate"};
+        }
+        // device copies of the program (small; allocated here, outside the workspace)
+        auto drop_region = [h](const void* p) {
+            h->regions.erase(std::remove_if(h->regions.begin(), h->regions.end(),
+                                            [p](const Region& r) { return r.lo == (uintptr_t)p; }),
+                             h->regions.end());
+        };
+        for (double** pp : {&h->d_omega, &h->d_delta, &h->d_evU}) {
+            if (*pp) {
+                drop_region(*pp);
+                if (!h->dry) HIPCHECK(hipFree(*pp));
+                *pp = nullptr;
+            }
+        }
+        const int dd = h->d * h->d;
+        const int64_t ns = std::max<int64_t>(1, (int64_t)h->N * n_seg);
+        const int64_t nu = std::max<int64_t>(1, (int64_t)n_events * 2 * dd);
+        if (h->dry) {
+            // distinct fake addresses far above the workspace, never dereferenced
+            const uintptr_t top = (h->regions.empty() ? 0 : h->regions.back().hi) + (uintptr_t(1) << 32);
+            h->d_omega = (double*)top;
+            h->d_delta = (double*)(top + (uintptr_t(1) << 30));
+            h->d_evU = (double*)(top + (uintptr_t(2) << 30));
+        } else {
+            HIPCHECK(hipMalloc(&h->d_omega, ns * sizeof(double)));
+            HIPCHECK(hipMalloc(&h->d_delta, ns * sizeof(double)));
+            HIPCHECK(hipMalloc(&h->d_evU, nu * sizeof(double)));
+            if (n_seg > 0) {
+                HIPCHECK(hipMemcpy(h->d_omega, omega, (int64_t)h->N * n_seg * sizeof(double), hipMemcpyHostToDevice));
+                HIPCHECK(hipMemcpy(h->d_delta, delta, (int64_t)h->N * n_seg * sizeof(double), hipMemcpyHostToDevice));
+            }
+        }
+        h->regions.push_back(Region{(uintptr_t)h->d_omega, (uintptr_t)h->d_omega + ns * sizeof(double)});
+        h->regions.push_back(Region{(uintptr_t)h->d_delta, (uintptr_t)h->d_delta + ns * sizeof(double)});
+        h->regions.push_back(Region{(uintptr_t)h->d_evU, (uintptr_t)h->d_evU + nu * sizeof(double)});
+        sort_regions(h);
+        h->n_seg = n_seg;
+        h->edges.assign(seg_edges, seg_edges + (n_seg > 0 ? n_seg + 1 : 0));
+        h->events.clear();
+        if (n_events > 0) {
+            std::vector<double> planar((int64_t)n_events * 2 * dd);
+            for (int e = 0; e < n_events; ++e)
+                for (int a = 0; a < h->d; ++a)
+                    for (int b2 = 0; b2 < h->d; ++b2) {
+                        const double* src = ev_u + (int64_t)e * 2 * dd + 2 * (a * h->d + b2);
+                        planar[(int64_t)e * 2 * dd + a + h->d * b2] = src[0];
+                        planar[(int64_t)e * 2 * dd + dd + a + h->d * b2] = src[1];
+                    }
+            if (!h->dry)
+                HIPCHECK(hipMemcpy(h->d_evU, planar.data(), planar.size() * sizeof(double), hipMemcpyHostToDevice));
+            for (int e = 0; e < n_events; ++e)
+                if (ev_step[e] >= h->step_count)
+                    h->events.push_back(Event{ev_step[e], ev_site[e], h->d_evU + (int64_t)e * 2 * dd, false});
+        }
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* stats) {
+    if (!h) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (!(dt > 0) || !std::isfinite(dt) || n_steps < 0) throw StatusError{TTN_EINVAL, "bad dt or n_steps"};
+        if (h->dt_set && dt != h->dt) throw StatusError{TTN_EINVAL, "dt must not change between calls"};
+        if (!h->d_omega) throw StatusError{TTN_ESTATE, "ttn_set_pulses must be called first"};
+        h->dt = dt;
+        h->dt_set = true;
+        for (int i = 0; i < n_steps; ++i) {
+            reset_step_dev(h);
+            apply_events_at(h, h->step_count);
+            const double t = ((double)h->step_count + 0.5) * dt;
+            set_hamiltonian(h, segment_at(h, t));
+            rebuild_up(h);
+            sweep_fwd(h, dt / 2);
+            sweep_bwd(h, dt / 2);
+            h->step_count += 1;
+            if (stats) {
+                StepDev s;
+                check_step_flags(h, &s);
+                ttn_step_stats& o = stats[i];
+                observables(h, &o.norm2, &o.energy);
+                std::memcpy(&o.min_r_diag, &s.min_rdiag_bits, sizeof(double));
+                o.min_krylov = s.min_krylov;
+                o.reserved = 0;
+                if (!h->dry && (!std::isfinite(o.norm2) || std::fabs(o.norm2 - 1.0) > 1e-6))
+                    throw StatusError{TTN_ENUMERIC, "norm drift beyond 1e-6"};
+            }
+        }
+        apply_events_at(h, h->step_count);
+        check_step_flags(h, nullptr);
+        if (!h->dry) HIPCHECK(hipGetLastError());
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_fidelity(ttn_handle* h, int32_t n_target, const int32_t* target_sites, double* F, double overlap[2]) {
+    if (!h || !F) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (n_target < 0 || (n_target > 0 && !target_sites)) throw StatusError{TTN_EINVAL, "bad target"};
+        std::vector<char> in(h->N, 0);
+        for (int i = 0; i < n_target; ++i) {
+            if (target_sites[i] < 0 || target_sites[i] >= h->N) throw StatusError{TTN_EINVAL, "bad target site"};
+            in[target_sites[i]] = 1;
+        }
+        const int d = h->d;
+        std::vector<double> zero((size_t)2 * h->N * d, 0.0), one((size_t)2 * h->N * d, 0.0);
+        for (int k = 0; k < h->N; ++k) {
+            zero[(size_t)2 * d * k + 0] = 1.0;
+            one[(size_t)2 * d * k + (in[h->leaf_site[k]] ? 1 : 0)] = 1.0;
+        }
+        double o0[2], o1[2];
+        product_overlap(h, zero, o0);
+        product_overlap(h, one, o1);
+        const double s = 1.0 / std::sqrt(2.0);
+        const double re = s * (o0[0] + o1[0]), im = s * (o0[1] + o1[1]);
+        *F = re * re + im * im;
+        if (overlap) {
+            overlap[0] = re;
+            overlap[1] = im;
+        }
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_observables(ttn_handle* h, double* norm2, double* energy) {
+    if (!h || !norm2 || !energy) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (h->cur_seg == -2) {
+            set_hamiltonian(h, h->d_omega ? segment_at(h, 0.0) : -1);
+            if (!h->d_omega) h->cur_seg = -1;
+            rebuild_up(h);
+        }
+        observables(h, norm2, energy);
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_local_expectation(ttn_handle* h, int32_t site, const double* op, double out[2]) {
+    if (!h || !op || !out) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (site < 0 || site >= h->N) throw StatusError{TTN_EINVAL, "bad site"};
+        const int d = h->d, dd = d * d;
+        std::vector<double> planar(2 * dd);
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                planar[a + d * b] = op[2 * (a * d + b)];
+                planar[dd + a + d * b] = op[2 * (a * d + b) + 1];
+            }
+        h2d(h, h->opbuf, planar.data(), planar.size() * sizeof(double));
+        int k = 0;
+        while (h->leaf_site[k] != site) ++k;
+        const int b = k / 2, side = k & 1;
+        Ctx<double> c{h, nullptr};
+        leg_apply<double>(c, side, h->opbuf, 0, h->T[b], 0, h->Ttmp, 0, h->DL[b], h->DR[b], h->DP[b], 1, 0);
+        ttn_contract(h, h, b, h->Ttmp, out);
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_overlap(ttn_handle* a, ttn_handle* b, double out[2]) {
+    if (!a || !b || !out) return TTN_EINVAL;
+    if (a->poisoned || b->poisoned) return TTN_ESTATE;
+    try {
+        if (a->N != b->N || a->d != b->d || a->chi != b->chi || a->leaf_site != b->leaf_site)
+            throw StatusError{TTN_EINVAL, "handles differ in shape"};
+        sync(b);
+        std::vector<Region> own = a->regions;
+        a->regions.insert(a->regions.end(), b->regions.begin(), b->regions.end());
+        sort_regions(a);
+        try {
+            ttn_contract(a, b, -1, nullptr, out);
+        } catch (...) {
+            a->regions = own;
+            sort_regions(a);
+            throw;
+        }
+        a->regions = own;
+        sort_regions(a);
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(a, e);
+    }
+}
+
+int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len) {
+    if (!h) return TTN_EINVAL;
+    int64_t total = 0;
+    for (int v = 0; v < h->n_nodes; ++v) total += nsize(h, v);
+    if (!host) return total;
+    if (h->poisoned) return TTN_ESTATE;
+    if (len < total) return TTN_EINVAL;
+    try {
+        int64_t o = 0;
+        std::vector<double> buf;
+        for (int v = 0; v < h->n_nodes; ++v) {
+            const int64_t n = nsize(h, v);
+            buf.resize(2 * n);
+            d2h(h, buf.data(), h->T[v], 2 * n * sizeof(double));
+            sync(h);
+            for (int64_t i = 0; i < n; ++i) {
+                host[2 * (o + i)] = buf[i];
+                host[2 * (o + i) + 1] = buf[n + i];
+            }
+            o += n;
+        }
+        return total;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t msg_len) {
+    ttn_handle* h = nullptr;
+    auto report = [&](const std::string& m) {
+        if (msg && msg_len > 0) snprintf(msg, msg_len, "%s", m.c_str());
+    };
+    try {
+        validate(cfg);
+        size_t bytes = 0;
+        int rc = ttn_workspace_query(cfg, &bytes);
+        if (rc != TTN_OK) return rc;
+        h = new ttn_handle();
+        h->dry = true;
+        g_dry_run = true;
+        setup_config(h, cfg);
+        void* fake = (void*)(uintptr_t(1) << 44);
+        Bump b(fake, bytes, &h->regions);
+        plan(h, b);
+        sort_regions(h);
+        build_couplings(h, cfg->pos_xy);
+        initial_tensors(h, cfg);
+        canonicalise(h);
+        // a program with one segment and one gate event on every leaf
+        const int N = h->N, d = h->d;
+        std::vector<double> edges = {0.0, 1e9}, om(N, 1.0), de(N, 0.5), u((size_t)N * 2 * d * d, 0.0);
+        std::vector<int32_t> st(N, 0), site(N);
+        for (int i = 0; i < N; ++i) {
+            site[i] = i;
+            for (int a = 0; a < d; ++a) u[(size_t)i * 2 * d * d + 2 * (a * d + a)] = 1.0;
+        }
+        rc = ttn_set_pulses(h, 1, edges.data(), om.data(), de.data(), N, st.data(), site.data(), u.data());
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        std::vector<ttn_step_stats> stats(std::max(1, n_steps));
+        rc = ttn_tdvp_step(h, 0.01, n_steps, stats.data());
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        double F, ov[2];
+        std::vector<int32_t> all(N);
+        for (int i = 0; i < N; ++i) all[i] = i;
+        rc = ttn_fidelity(h, N, all.data(), &F, ov);
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        std::vector<double> op((size_t)2 * d * d, 0.0);
+        rc = ttn_local_expectation(h, N - 1, op.data(), ov);
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        rc = ttn_overlap(h, h, ov);
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        g_dry_run = false;
+        report("ok");
+        delete h;
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        g_dry_run = false;
+        report(e.msg);
+        delete h;
+        return e.code;
+    } catch (...) {
+        g_dry_run = false;
+        report("unexpected exception");
+        delete h;
+        return TTN_EINVAL;
+    }
+}
+
+int ttn_backward(ttn_handle* h, double dF, double* grad_omega, double* grad_delta) {
+    (void)dF;
+    (void)grad_omega;
+    (void)grad_delta;
+    if (!h) return TTN_EINVAL;
+    h->err = "ttn_backward is not available in this build";
+    return TTN_ENOTSUP;
+}
+
+int ttn_destroy(ttn_handle* h) {
+    if (!h) return TTN_EINVAL;
+    if (!h->dry) {
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        if (h->d_omega) (void)hipFree(h->d_omega);
+        if (h->d_delta) (void)hipFree(h->d_delta);
+        if (h->d_evU) (void)hipFree(h->d_evU);
+    }
+    delete h;
+    return TTN_OK;
+}
+
+const char* ttn_last_error(const ttn_handle* h) {
+    if (!h) return g_init_error.c_str();
+    return h->err.c_str();
+}
+
+}  // extern "C"

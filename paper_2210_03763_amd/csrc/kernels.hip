@@ -1,0 +1,781 @@
+// Device kernels of the TTN/TDVP library for gfx950 (CDNA4, wave64).
+//
+// Generic strided planar-complex GEMM (4M: four real products per complex
+// product), split-K with a deterministic second-stage reduction; Lanczos
+// reductions with device-resident scalars; Cholesky + triangular inverse for
+// CholeskyQR2 gauge moves; the tridiagonal exponential of the Krylov
+// projection via a Jacobi eigendecomposition; small helpers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+
+#include "ttn_internal.h"
+
+namespace ttn {
+
+namespace {
+
+constexpr int GEMM_THREADS = 256;
+
+template <typename R, int BM, int BN, int BK>
+__global__ __launch_bounds__(GEMM_THREADS) void k_cgemm(Gemm<R> g, int tilesM, int tilesN,
+                                                        int splits, int kchunk, R* partial,
+                                                        int a_mfast, int b_nfast) {
+    if (g.skip && *g.skip) return;
+    constexpr int TM = BM / 16, TN = BN / 16;
+    __shared__ R As[2][BK][BM + 1];
+    __shared__ R Bs[2][BK][BN + 1];
+    int64_t bid = blockIdx.x;
+    const int tm = bid % tilesM;
+    bid /= tilesM;
+    const int tn = bid % tilesN;
+    bid /= tilesN;
+    const int sp = bid % splits;
+    bid /= splits;
+    const int b = (int)bid;
+    const int b1 = b % g.B1, b2 = b / g.B1;
+    const R* A = g.A + b1 * g.sab1 + b2 * g.sab2;
+    const R* B = g.B + b1 * g.sbb1 + b2 * g.sbb2;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int K = g.Kin * g.Kout;
+    const int kb = sp * kchunk;
+    const int ke = min(K, kb + kchunk);
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
+    R acc_re[TM][TN], acc_im[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            acc_re[i][j] = 0;
+            acc_im[i][j] = 0;
+        }
+    const R sa = g.conjA ? R(-1) : R(1);
+    const R sb = g.conjB ? R(-1) : R(1);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        for (int e = tid; e < BM * BK; e += GEMM_THREADS) {
+            int mm, kk;
+            if (a_mfast) {
+                mm = e % BM;
+                kk = e / BM;
+            } else {
+                kk = e % BK;
+                mm = e / BK;
+            }
+            const int m = m0 + mm, k = k0 + kk;
+            R re = 0, im = 0;
+            if (m < g.M && k < ke) {
+                const int kin = k % g.Kin, kout = k / g.Kin;
+                const int64_t off = (int64_t)m * g.sam + (int64_t)kin * g.sak + (int64_t)kout * g.sako;
+                re = A[off];
+                im = sa * A[off + g.a_plane];
+            }
+            As[0][kk][mm] = re;
+            As[1][kk][mm] = im;
+        }
+        for (int e = tid; e < BN * BK; e += GEMM_THREADS) {
+            int nn, kk;
+            if (b_nfast) {
+                nn = e % BN;
+                kk = e / BN;
+            } else {
+                kk = e % BK;
+                nn = e / BK;
+            }
+            const int n = n0 + nn, k = k0 + kk;
+            R re = 0, im = 0;
+            if (n < g.N && k < ke) {
+                const int kin = k % g.Kin, kout = k / g.Kin;
+                const int64_t off = (int64_t)n * g.sbn + (int64_t)kin * g.sbk + (int64_t)kout * g.sbko;
+                re = B[off];
+                im = sb * B[off + g.b_plane];
+            }
+            Bs[0][kk][nn] = re;
+            Bs[1][kk][nn] = im;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < BK; ++kk) {
+            R ar[TM], ai[TM], br[TN], bi[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                ar[i] = As[0][kk][tx + 16 * i];
+                ai[i] = As[1][kk][tx + 16 * i];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                br[j] = Bs[0][kk][ty + 16 * j];
+                bi[j] = Bs[1][kk][ty + 16 * j];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    acc_re[i][j] = fma(ar[i], br[j], acc_re[i][j]);
+                    acc_re[i][j] = fma(-ai[i], bi[j], acc_re[i][j]);
+                    acc_im[i][j] = fma(ar[i], bi[j], acc_im[i][j]);
+                    acc_im[i][j] = fma(ai[i], br[j], acc_im[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+    if (splits == 1) {
+        R* C = g.C + b1 * g.scb1 + b2 * g.scb2;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int m = m0 + tx + 16 * i;
+            if (m >= g.M) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + ty + 16 * j;
+                if (n >= g.N) continue;
+                const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
+                R re = g.alpha * acc_re[i][j], im = g.alpha * acc_im[i][j];
+                if (g.beta) {
+                    re += C[off];
+                    im += C[off + g.c_plane];
+                }
+                C[off] = re;
+                C[off + g.c_plane] = im;
+            }
+        }
+    } else {
+        const int64_t MN = (int64_t)g.M * g.N;
+        const int nbatch = g.B1 * g.B2;
+        R* P = partial + ((int64_t)sp * nbatch + b) * 2 * MN;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int m = m0 + tx + 16 * i;
+            if (m >= g.M) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + ty + 16 * j;
+                if (n >= g.N) continue;
+                P[m + (int64_t)g.M * n] = acc_re[i][j];
+                P[MN + m + (int64_t)g.M * n] = acc_im[i][j];
+            }
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_splitk_reduce(Gemm<R> g, int splits, const R* partial) {
+    if (g.skip && *g.skip) return;
+    const int64_t MN = (int64_t)g.M * g.N;
+    const int nbatch = g.B1 * g.B2;
+    const int64_t total = MN * nbatch;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / MN);
+        const int64_t mn = e % MN;
+        const int m = (int)(mn % g.M), n = (int)(mn / g.M);
+        R re = 0, im = 0;
+        for (int s = 0; s < splits; ++s) {
+            const R* P = partial + ((int64_t)s * nbatch + b) * 2 * MN;
+            re += P[mn];
+            im += P[MN + mn];
+        }
+        const int b1 = b % g.B1, b2 = b / g.B1;
+        R* C = g.C + b1 * g.scb1 + b2 * g.scb2;
+        const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
+        re *= g.alpha;
+        im *= g.alpha;
+        if (g.beta) {
+            re += C[off];
+            im += C[off + g.c_plane];
+        }
+        C[off] = re;
+        C[off + g.c_plane] = im;
+    }
+}
+
+// Largest element offset an operand can touch (all strides are >= 0).
+inline bool inside(const GemmScratch& ws, const void* base, int64_t max_off, int64_t plane, int esz) {
+    if (!ws.regions) return true;
+    const uintptr_t p = (uintptr_t)base;
+    int lo = 0, hi = ws.n_regions - 1, f = -1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) / 2;
+        if (ws.regions[mid].lo <= p) {
+            f = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (f < 0) return false;
+    const uintptr_t end = p + (uintptr_t)(max_off + plane + 1) * esz;
+    return p >= ws.regions[f].lo && end <= ws.regions[f].hi;
+}
+
+}  // namespace
+
+bool g_dry_run = false;
+
+template <typename R>
+bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen) {
+    if (g.M <= 0 || g.N <= 0 || g.B1 * g.B2 <= 0) return true;
+    {
+        const int64_t km = g.Kin > 0 ? g.Kin - 1 : 0, ko = g.Kout > 0 ? g.Kout - 1 : 0;
+        const int64_t b1 = g.B1 - 1, b2 = g.B2 - 1;
+        const int64_t amax = (g.M - 1) * g.sam + km * g.sak + ko * g.sako + b1 * g.sab1 + b2 * g.sab2;
+        const int64_t bmax = (g.N - 1) * g.sbn + km * g.sbk + ko * g.sbko + b1 * g.sbb1 + b2 * g.sbb2;
+        const int64_t cmax = (g.M - 1) * g.scm + (g.N - 1) * g.scn + b1 * g.scb1 + b2 * g.scb2;
+        const bool neg = g.sam < 0 || g.sak < 0 || g.sako < 0 || g.sab1 < 0 || g.sab2 < 0 || g.sbn < 0 ||
+                         g.sbk < 0 || g.sbko < 0 || g.sbb1 < 0 || g.sbb2 < 0 || g.scm < 0 || g.scn < 0 ||
+                         g.scb1 < 0 || g.scb2 < 0 || g.a_plane < 0 || g.b_plane < 0 || g.c_plane < 0;
+        const char* bad = neg ? "negative stride"
+                          : !inside(ws, g.A, amax, g.a_plane, sizeof(R)) ? "operand A out of its region"
+                          : !inside(ws, g.B, bmax, g.b_plane, sizeof(R)) ? "operand B out of its region"
+                          : !inside(ws, g.C, cmax, g.c_plane, sizeof(R)) ? "operand C out of its region"
+                                                                         : nullptr;
+        if (bad) {
+            if (why)
+                snprintf(why, whylen, "%s (M=%d N=%d Kin=%d Kout=%d B=%dx%d)", bad, g.M, g.N, g.Kin, g.Kout,
+                         g.B1, g.B2);
+            return false;
+        }
+    }
+    if (g_dry_run) return true;
+    const int K = g.Kin * g.Kout;
+    constexpr int BM = 64, BN = 64, BK = 16;
+    const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
+    const int64_t nbatch = (int64_t)g.B1 * g.B2;
+    const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
+    int splits = 1;
+    if (K > 0 && tiles < 512 && K > 4 * BK) {
+        splits = (int)std::min<int64_t>((1024 + tiles - 1) / tiles, K / (2 * BK));
+        const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
+        const int64_t cap = per > 0 ? ws.bytes / per : 1;
+        if (splits > cap) splits = (int)cap;
+        if (splits < 1) splits = 1;
+    }
+    int kchunk = K;
+    if (splits > 1) {
+        kchunk = ((K + splits - 1) / splits + BK - 1) / BK * BK;
+        splits = (K + kchunk - 1) / kchunk;
+    }
+    if (K == 0) kchunk = 0;
+    const int a_mfast = (g.sam == 1 || g.sak != 1) ? 1 : 0;
+    const int b_nfast = (g.sbn == 1 || g.sbk != 1) ? 1 : 0;
+    const int64_t blocks = tiles * splits;
+    hipLaunchKernelGGL((k_cgemm<R, BM, BN, BK>), dim3((unsigned)blocks), dim3(GEMM_THREADS), 0, s, g,
+                       tilesM, tilesN, splits, kchunk, (R*)ws.partial, a_mfast, b_nfast);
+    if (splits > 1) {
+        const int64_t total = (int64_t)g.M * g.N * nbatch;
+        const int nb = (int)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL((k_splitk_reduce<R>), dim3(nb), dim3(256), 0, s, g, splits,
+                           (const R*)ws.partial);
+    }
+    return true;
+}
+
+template bool cgemm<double>(const Gemm<double>&, const GemmScratch&, hipStream_t, char*, int);
+template bool cgemm<float>(const Gemm<float>&, const GemmScratch&, hipStream_t, char*, int);
+
+// ---------------------------------------------------------------------------
+// reductions for Lanczos
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int RED_THREADS = 256;
+
+__device__ inline double block_sum(double v, double* sh) {
+    // wave64 shuffle reduction, then across the four waves of the block
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x / 64); ++i) r += sh[i];
+    return r;   // valid in thread 0
+}
+
+__global__ void k_norm2_partial(const double* x, int64_t n, double* partial, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double sh[16];
+    double acc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = x[i], b = x[i + n];
+        acc += a * a + b * b;
+    }
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ void k_sum_partial(const double* partial, int nb, double* out, const int* skip) {
+    if (skip && *skip) return;
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < nb; ++i) s += partial[i];
+        *out = s;
+    }
+}
+
+__global__ void k_lz_begin(const double* partial, int nb, LanczosDev* lz) {
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < nb; ++i) s += partial[i];
+        lz->beta0 = sqrt(s);
+        lz->zero = (s == 0.0) ? 1 : 0;
+        lz->done = lz->zero;
+        lz->m_eff = 0;
+    }
+}
+
+__global__ void k_scale_by(const double* x, int64_t n, double* y, const LanczosDev* lz, int use_beta0,
+                           int j) {
+    if (lz->done) return;
+    const double s = 1.0 / (use_beta0 ? lz->beta0 : lz->beta[j]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i] * s;
+}
+
+// partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < kcount
+__global__ void k_multidot_partial(const double* V, int kcount, const double* w, int64_t n,
+                                   double* partial, const LanczosDev* lz) {
+    if (lz->done) return;
+    __shared__ double sh[16];
+    double re[KRYLOV_MAX], im[KRYLOV_MAX];
+    for (int k = 0; k < KRYLOV_MAX; ++k) re[k] = im[k] = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double wr = w[i], wi = w[i + n];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k) {
+            if (k < kcount) {
+                const double* v = V + 2 * n * k;
+                const double vr = v[i], vi = v[i + n];
+                re[k] += vr * wr + vi * wi;
+                im[k] += vr * wi - vi * wr;
+            }
+        }
+    }
+    for (int k = 0; k < kcount; ++k) {
+        const double a = block_sum(re[k], sh);
+        if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2] = a;
+        const double b = block_sum(im[k], sh);
+        if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2 + 1] = b;
+    }
+}
+
+__global__ void k_multidot_final(const double* partial, int nb, int kcount, LanczosDev* lz,
+                                 int alpha_index) {
+    if (lz->done) return;
+    const int k = threadIdx.x;
+    if (k < kcount) {
+        double re = 0, im = 0;
+        for (int b = 0; b < nb; ++b) {
+            re += partial[(b * KRYLOV_MAX + k) * 2];
+            im += partial[(b * KRYLOV_MAX + k) * 2 + 1];
+        }
+        lz->c[2 * k] = re;
+        lz->c[2 * k + 1] = im;
+        if (k == alpha_index) {
+            lz->alpha[k] = re;
+            lz->m_eff = k + 1;
+        }
+    }
+}
+
+__global__ void k_multi_subtract(const double* V, int kcount, double* w, int64_t n,
+                                 const LanczosDev* lz) {
+    if (lz->done) return;
+    __shared__ double c[2 * KRYLOV_MAX];
+    if (threadIdx.x < 2 * KRYLOV_MAX) c[threadIdx.x] = lz->c[threadIdx.x];
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double wr = w[i], wi = w[i + n];
+        for (int k = 0; k < kcount; ++k) {
+            const double* v = V + 2 * n * k;
+            const double vr = v[i], vi = v[i + n];
+            const double cr = c[2 * k], ci = c[2 * k + 1];
+            wr -= cr * vr - ci * vi;
+            wi -= cr * vi + ci * vr;
+        }
+        w[i] = wr;
+        w[i + n] = wi;
+    }
+}
+
+__global__ void k_lz_beta(const double* partial, int nb, LanczosDev* lz, int j, double tol) {
+    if (lz->done) return;
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < nb; ++i) s += partial[i];
+        const double b = sqrt(s);
+        const double bprev = j > 0 ? lz->beta[j - 1] : 0.0;
+        if (!(b > tol * (fabs(lz->alpha[j]) + bprev)))
+            lz->done = 1;
+        else
+            lz->beta[j] = b;
+    }
+}
+
+// exp(-i tau T) e_1 for the real symmetric tridiagonal T (alpha, beta) of
+// size m_eff, by cyclic Jacobi rotations: T = U diag(lambda) U^T.
+__global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
+    if (threadIdx.x != 0 || lz->zero) return;
+    const int m = lz->m_eff;
+    double a[KRYLOV_MAX][KRYLOV_MAX], u[KRYLOV_MAX][KRYLOV_MAX];
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            a[i][j] = 0;
+            u[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int i = 0; i < m; ++i) a[i][i] = lz->alpha[i];
+    for (int i = 0; i + 1 < m; ++i) a[i][i + 1] = a[i + 1][i] = lz->beta[i];
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0, dg = 0;
+        for (int p = 0; p < m; ++p) {
+            dg += a[p][p] * a[p][p];
+            for (int q = p + 1; q < m; ++q) off += a[p][q] * a[p][q];
+        }
+        if (off <= 1e-34 * dg || off == 0.0) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = a[p][q];
+                if (apq == 0.0) continue;
+                const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < m; ++k) {   // columns p, q
+                    const double akp = a[k][p], akq = a[k][q];
+                    a[k][p] = c * akp - s * akq;
+                    a[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < m; ++k) {   // rows p, q
+                    const double apk = a[p][k], aqk = a[q][k];
+                    a[p][k] = c * apk - s * aqk;
+                    a[q][k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < m; ++k) {
+                    const double ukp = u[k][p], ukq = u[k][q];
+                    u[k][p] = c * ukp - s * ukq;
+                    u[k][q] = s * ukp + c * ukq;
+                }
+            }
+    }
+    for (int i = 0; i < m; ++i) {
+        double yr = 0, yi = 0;
+        for (int k = 0; k < m; ++k) {
+            const double ph = -tau * a[k][k];
+            const double w = u[i][k] * u[0][k];
+            yr += w * cos(ph);
+            yi += w * sin(ph);
+        }
+        lz->y[2 * i] = yr;
+        lz->y[2 * i + 1] = yi;
+    }
+    atomicMin(&st->min_krylov, m);
+}
+
+__global__ void k_lz_combine(const double* V, int64_t n, double* out, const LanczosDev* lz) {
+    if (lz->zero) return;
+    __shared__ double y[2 * KRYLOV_MAX];
+    const int m = lz->m_eff;
+    if (threadIdx.x < 2 * KRYLOV_MAX) y[threadIdx.x] = lz->y[threadIdx.x] * lz->beta0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0, im = 0;
+        for (int k = 0; k < m; ++k) {
+            const double* v = V + 2 * n * k;
+            const double vr = v[i], vi = v[i + n];
+            re += y[2 * k] * vr - y[2 * k + 1] * vi;
+            im += y[2 * k] * vi + y[2 * k + 1] * vr;
+        }
+        out[i] = re;
+        out[i + n] = im;
+    }
+}
+
+inline int grid_for(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
+}
+
+}  // namespace
+
+void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_sum, const int* skip,
+               hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, x, n, partial, skip);
+    hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(64), 0, s, partial, nb, out_sum, skip);
+}
+
+void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
+              hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, x, n, partial,
+                       (const int*)nullptr);
+    hipLaunchKernelGGL(k_lz_begin, dim3(1), dim3(64), 0, s, partial, nb, lz);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, x, n, v0, lz, 1, 0);
+}
+
+void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
+                LanczosDev* lz, int alpha_index, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_multidot_partial, dim3(nb), dim3(RED_THREADS), 0, s, V, kcount, w, n,
+                       partial, lz);
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64), 0, s, partial, nb, kcount, lz,
+                       alpha_index);
+}
+
+void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_multi_subtract, dim3(grid_for(n)), dim3(256), 0, s, V, kcount, w, n, lz);
+}
+
+void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
+             double tol, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, w, n, partial, &lz->done);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s, partial, nb, lz, j, tol);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j);
+}
+
+void lz_expm(LanczosDev* lz, double tau, StepDev* st, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_lz_expm, dim3(1), dim3(64), 0, s, lz, tau, st);
+}
+
+void lz_combine(const double* V, int64_t n, double* out, LanczosDev* lz, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_lz_combine, dim3(grid_for(n)), dim3(256), 0, s, V, n, out, lz);
+}
+
+// ---------------------------------------------------------------------------
+// conversions / copies
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void k_d2f(const double* x, float* y, int64_t c, const int* skip) {
+    if (skip && *skip) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+__global__ void k_f2d(const float* x, double* y, int64_t c, const int* skip) {
+    if (skip && *skip) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+__global__ void k_copy(const double* x, double* y, int64_t c, const int* skip) {
+    if (skip && *skip) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+__global__ void k_zero(double* y, int64_t c) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = 0.0;
+}
+// y[c + cols*r] = x[r + rows*c] (planar complex, column-major)
+__global__ void k_transpose(const double* x, double* y, int rows, int cols) {
+    const int64_t n = (int64_t)rows * cols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e % rows), c = (int)(e / rows);
+        y[c + (int64_t)cols * r] = x[e];
+        y[n + c + (int64_t)cols * r] = x[n + e];
+    }
+}
+}  // namespace
+
+void convert_d2f(const double* x, float* y, int64_t count, const int* skip, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_d2f, dim3(grid_for(count)), dim3(256), 0, s, x, y, count, skip);
+}
+void convert_f2d(const float* x, double* y, int64_t count, const int* skip, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_f2d, dim3(grid_for(count)), dim3(256), 0, s, x, y, count, skip);
+}
+void copy_d(const double* x, double* y, int64_t count, const int* skip, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(count)), dim3(256), 0, s, x, y, count, skip);
+}
+void fill_zero_d(double* y, int64_t count, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(count)), dim3(256), 0, s, y, count);
+}
+void transpose_c(const double* x, double* y, int rows, int cols, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_transpose, dim3(grid_for((int64_t)rows * cols)), dim3(256), 0, s, x, y,
+                       rows, cols);
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky + inverse for CholeskyQR2
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int CHOL_THREADS = 512;
+constexpr int CHOL_LDS_MAX = 128;   // packed lower triangle of 128 x 128 fits LDS
+
+__device__ inline int64_t pidx(int i, int j, int D) {   // packed lower, column-major, i >= j
+    return (int64_t)j * D - (int64_t)j * (j - 1) / 2 + (i - j);
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int D, double* Linv,
+                                                           double* R, const double* Rprev,
+                                                           double* work, StepDev* st) {
+    __shared__ double sLre[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) / 2 : 1];
+    __shared__ double sLim[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) / 2 : 1];
+    __shared__ int s_bad;
+    const int64_t np = (int64_t)D * (D + 1) / 2;
+    double* Lre = LDS ? sLre : work;
+    double* Lim = LDS ? sLim : work + np;
+    const int tid = threadIdx.x;
+    const int64_t DD = (int64_t)D * D;
+    if (tid == 0) s_bad = 0;
+    for (int j = 0; j < D; ++j)
+        for (int i = j + tid; i < D; i += CHOL_THREADS) {
+            Lre[pidx(i, j, D)] = G[i + (int64_t)D * j];
+            Lim[pidx(i, j, D)] = G[DD + i + (int64_t)D * j];
+        }
+    __syncthreads();
+    for (int j = 0; j < D; ++j) {
+        const int64_t jj = pidx(j, j, D);
+        if (tid == 0) {
+            const double piv = Lre[jj];
+            if (!(piv > 1e-290)) s_bad = 1;
+            Lre[jj] = sqrt(piv > 1e-290 ? piv : 1e-290);
+            Lim[jj] = 0.0;
+        }
+        __syncthreads();
+        const double dinv = 1.0 / Lre[jj];
+        for (int i = j + 1 + tid; i < D; i += CHOL_THREADS) {
+            Lre[pidx(i, j, D)] *= dinv;
+            Lim[pidx(i, j, D)] *= dinv;
+        }
+        __syncthreads();
+        const int rn = D - j - 1;
+        for (int e = tid; e < rn * rn; e += CHOL_THREADS) {
+            const int ii = e % rn, kk = e / rn;
+            if (ii < kk) continue;
+            const int i = j + 1 + ii, k = j + 1 + kk;
+            const double ar = Lre[pidx(i, j, D)], ai = Lim[pidx(i, j, D)];
+            const double br = Lre[pidx(k, j, D)], bi = Lim[pidx(k, j, D)];
+            // L[i][k] -= L[i][j] * conj(L[k][j])
+            Lre[pidx(i, k, D)] -= ar * br + ai * bi;
+            Lim[pidx(i, k, D)] -= ai * br - ar * bi;
+        }
+        __syncthreads();
+    }
+    // X = L^{-1}, lower triangular, row by row: X[i][j] = -(sum_{k=j}^{i-1} L[i][k] X[k][j]) / L[i][i]
+    double* Xr = Linv;
+    double* Xi = Linv + DD;
+    for (int e = tid; e < DD; e += CHOL_THREADS) {
+        Xr[e] = 0.0;
+        Xi[e] = 0.0;
+    }
+    __syncthreads();
+    for (int i = 0; i < D; ++i) {
+        const double lii = Lre[pidx(i, i, D)];
+        for (int j = tid; j <= i; j += CHOL_THREADS) {
+            if (j == i) {
+                Xr[i + (int64_t)D * i] = 1.0 / lii;
+                continue;
+            }
+            double sr = 0, si = 0;
+            for (int k = j; k < i; ++k) {
+                const double lr = Lre[pidx(i, k, D)], li = Lim[pidx(i, k, D)];
+                const double xr = Xr[k + (int64_t)D * j], xi = Xi[k + (int64_t)D * j];
+                sr += lr * xr - li * xi;
+                si += lr * xi + li * xr;
+            }
+            Xr[i + (int64_t)D * j] = -sr / lii;
+            Xi[i + (int64_t)D * j] = -si / lii;
+        }
+        __syncthreads();
+    }
+    // R = L^H (upper), optionally times Rprev (upper): R[k][a] = sum_{j=k}^{a} conj(L[j][k]) Rprev[j][a]
+    for (int e = tid; e < DD; e += CHOL_THREADS) {
+        const int k = (int)(e % D), a = (int)(e / D);
+        double rr = 0, ri = 0;
+        if (a >= k) {
+            if (!Rprev) {
+                rr = Lre[pidx(a, k, D)];
+                ri = -Lim[pidx(a, k, D)];
+            } else {
+                for (int j = k; j <= a; ++j) {
+                    const double lr = Lre[pidx(j, k, D)], li = -Lim[pidx(j, k, D)];
+                    const double pr = Rprev[j + (int64_t)D * a], pi = Rprev[DD + j + (int64_t)D * a];
+                    rr += lr * pr - li * pi;
+                    ri += lr * pi + li * pr;
+                }
+            }
+        }
+        R[e] = rr;
+        R[DD + e] = ri;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double mn = 1e308;
+        for (int k = 0; k < D; ++k) {
+            const double v = R[k + (int64_t)D * k];
+            mn = v < mn ? v : mn;
+        }
+        if (s_bad || !(mn == mn)) atomicExch(&st->bad, 1);
+        if (mn > 0) atomicMin(&st->min_rdiag_bits, (unsigned long long)__double_as_longlong(mn));
+    }
+}
+
+}  // namespace
+
+void chol_inv(const double* G, int D, double* Linv, double* R, const double* Rprev, double* work,
+              StepDev* st, hipStream_t s) {
+    if (g_dry_run) return;
+    if (D <= CHOL_LDS_MAX)
+        hipLaunchKernelGGL(k_chol_inv<true>, dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R, Rprev,
+                           work, st);
+    else
+        hipLaunchKernelGGL(k_chol_inv<false>, dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R,
+                           Rprev, work, st);
+}
+
+// ---------------------------------------------------------------------------
+// leaf operator blocks and product-state contractions
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void k_contract_node_vec(const double* T, int DL, int DR, int DP, const double* a,
+                                    const double* b, double* out) {
+    __shared__ double sh[16];
+    const int p = blockIdx.x;
+    const int64_t n = (int64_t)DL * DR * DP;
+    const int64_t LR = (int64_t)DL * DR;
+    double re = 0, im = 0;
+    for (int64_t e = threadIdx.x; e < LR; e += blockDim.x) {
+        const int l = (int)(e % DL), r = (int)(e / DL);
+        const double ar = a[l], ai = a[l + DL], br = b[r], bi = b[r + DR];
+        const double abr = ar * br - ai * bi, abi = ar * bi + ai * br;
+        const double tr = T[e + LR * p], ti = T[n + e + LR * p];
+        re += abr * tr - abi * ti;
+        im += abr * ti + abi * tr;
+    }
+    const double sr = block_sum(re, sh);
+    const double si = block_sum(im, sh);
+    if (threadIdx.x == 0) {
+        out[p] = sr;
+        out[p + DP] = si;
+    }
+}
+}  // namespace
+
+void contract_node_vec(const double* T, int DL, int DR, int DP, const double* a, const double* b,
+                       double* out, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_contract_node_vec, dim3(DP), dim3(256), 0, s, T, DL, DR, DP, a, b, out);
+}
+
+}  // namespace ttn

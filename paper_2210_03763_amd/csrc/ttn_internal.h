@@ -1,0 +1,113 @@
+// Internal interfaces of the TTN/TDVP device library (gfx950).
+//
+// Storage convention: a complex array of n elements is n real parts followed
+// by n imaginary parts ("planar"); stacks of such arrays are concatenated,
+// so slot k of a stack of n-element arrays starts at 2*n*k.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ttn {
+
+constexpr int KRYLOV_MAX = 16;
+
+// Strided, batched, planar-complex GEMM:
+//   C[m, n] = alpha * sum_k opA[m, k] opB[k, n] + beta * C[m, n]
+// with k = k_in + Kin * k_out (two-level contraction index) and batch
+// b = b1 + B1 * b2.  Offsets are in real elements; *_plane is the distance
+// from a real part to its imaginary part.
+template <typename R>
+struct Gemm {
+    int M = 0, N = 0, Kin = 1, Kout = 1, B1 = 1, B2 = 1;
+    const R* A = nullptr;
+    int64_t a_plane = 0, sam = 0, sak = 0, sako = 0, sab1 = 0, sab2 = 0;
+    bool conjA = false;
+    const R* B = nullptr;
+    int64_t b_plane = 0, sbk = 0, sbko = 0, sbn = 0, sbb1 = 0, sbb2 = 0;
+    bool conjB = false;
+    R* C = nullptr;
+    int64_t c_plane = 0, scm = 0, scn = 0, scb1 = 0, scb2 = 0;
+    R alpha = 1;
+    int beta = 0;                 // 0 overwrite, 1 accumulate
+    const int* skip = nullptr;    // device flag: launch is a no-op when set
+};
+
+// A device allocation [lo, hi) of the workspace, for launch extent checks.
+struct Region {
+    uintptr_t lo, hi;
+};
+
+// Scratch for split-K partial sums (real elements) owned by the engine, and
+// the table of workspace regions every GEMM operand must stay inside.
+struct GemmScratch {
+    void* partial = nullptr;
+    int64_t bytes = 0;
+    const Region* regions = nullptr;   // sorted by lo
+    int n_regions = 0;
+};
+
+// Validates every operand extent against the region table and launches.
+// Returns false (and launches nothing) when an operand would leave its
+// region; `why` receives a description.
+template <typename R>
+bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen);
+
+// When set, launchers validate but enqueue nothing (plan checking without a
+// device).
+extern bool g_dry_run;
+
+// Lanczos state kept on the device so that no host round trip is needed.
+struct LanczosDev {
+    double beta0;
+    double alpha[KRYLOV_MAX];
+    double beta[KRYLOV_MAX];
+    double c[2 * KRYLOV_MAX];
+    double y[2 * KRYLOV_MAX];
+    int m_eff;
+    int done;
+    int zero;
+    int pad;
+};
+
+// Step-level device flags and statistics.
+struct StepDev {
+    int bad;                 // non-zero after a failed Cholesky pivot / NaN
+    int min_krylov;
+    unsigned long long min_rdiag_bits;   // positive double as ordered bits
+    double scratch[8];
+};
+
+// reductions / vector kernels (double master vectors)
+void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_sum,
+               const int* skip, hipStream_t s);
+void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
+              hipStream_t s);
+void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
+                LanczosDev* lz, int alpha_index, hipStream_t s);
+void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s);
+void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
+             double tol, hipStream_t s);
+void lz_expm(LanczosDev* lz, double tau, StepDev* st, hipStream_t s);
+void lz_combine(const double* V, int64_t n, double* out, LanczosDev* lz, hipStream_t s);
+
+// conversions and copies
+void convert_d2f(const double* x, float* y, int64_t count, const int* skip, hipStream_t s);
+void convert_f2d(const float* x, double* y, int64_t count, const int* skip, hipStream_t s);
+void copy_d(const double* x, double* y, int64_t count, const int* skip, hipStream_t s);
+void transpose_c(const double* x, double* y, int rows, int cols, hipStream_t s);
+void fill_zero_d(double* y, int64_t count, hipStream_t s);
+
+// Cholesky of a Hermitian D x D Gram matrix G (planar, column-major):
+// G = L L^H.  Writes Linv (lower, L^{-1}) and R = L^H (upper), or R = L^H * Rprev
+// when Rprev != nullptr.  Sets st->bad on a non-positive pivot.
+void chol_inv(const double* G, int D, double* Linv, double* R, const double* Rprev, double* work,
+              StepDev* st, hipStream_t s);
+
+// out[p] = sum_{l,r} a[l] b[r] T[l, r, p] (planar complex vectors); used for
+// overlaps with product states.
+void contract_node_vec(const double* T, int DL, int DR, int DP, const double* a, const double* b,
+                       double* out, hipStream_t s);
+
+}  // namespace ttn

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libttn.so (include/ttn.h).
+
+Argument marshalling only: every step of the TDVP path runs in the HIP
+kernels of the library.  PyTorch provides the device workspace and the
+stream.  The library must be built (paper_2210_03763_amd.build); nothing
+here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttn.so")
+
+TTN_OK, TTN_EINVAL, TTN_ENOMEM, TTN_EDEVICE, TTN_ENUMERIC, TTN_ESTATE, TTN_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_FP32 = 0, 1
+
+_ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "ESTATE", -6: "ENOTSUP"}
+
+
+class TTNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("n_sites", C.c_int32), ("d", C.c_int32), ("chi", C.c_int32),
+                ("krylov_dim", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("c6", C.c_double), ("r_cut", C.c_double), ("leak_ratio", C.c_double),
+                ("pos_xy", C.POINTER(C.c_double)), ("leaf_order", C.POINTER(C.c_int32)),
+                ("init_product", C.POINTER(C.c_double)), ("dress_eps", C.c_double),
+                ("dress_noise", C.POINTER(C.c_double)), ("dress_noise_len", C.c_int64)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("norm2", C.c_double), ("energy", C.c_double), ("min_r_diag", C.c_double),
+                ("min_krylov", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libttn.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime under the same soname; importing it
+        # first makes this library bind to that runtime instead of loading a
+        # second one from the system path (two runtimes cannot share a device)
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: run paper_2210_03763_amd.build.build() first")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        DP = C.POINTER(C.c_double)
+        IP = C.POINTER(C.c_int32)
+        sig = {
+            "ttn_workspace_query": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_size_t)]),
+            "ttn_init": (C.c_int, [C.POINTER(Config), P, C.c_size_t, P, C.POINTER(P)]),
+            "ttn_set_pulses": (C.c_int, [P, I32, DP, DP, DP, I32, IP, IP, DP]),
+            "ttn_tdvp_step": (C.c_int, [P, D, I32, C.POINTER(StepStats)]),
+            "ttn_fidelity": (C.c_int, [P, I32, IP, DP, DP]),
+            "ttn_observables": (C.c_int, [P, DP, DP]),
+            "ttn_local_expectation": (C.c_int, [P, I32, DP, DP]),
+            "ttn_overlap": (C.c_int, [P, P, DP]),
+            "ttn_export_state": (I64, [P, DP, I64]),
+            "ttn_backward": (C.c_int, [P, D, DP, DP]),
+            "ttn_destroy": (C.c_int, [P]),
+            "ttn_last_error": (C.c_char_p, [P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _complex_interleaved(a) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    return a.view(np.float64).reshape(-1).copy()
+
+
+def make_config(w, keep: list) -> Config:
+    """ttn_config from a workload description; `keep` holds the arrays alive."""
+    pos = np.ascontiguousarray(w.pos_xy, dtype=np.float64).reshape(-1)
+    order = np.ascontiguousarray(w.leaf_order, dtype=np.int32)
+    prod = _complex_interleaved(w.init_product)
+    noise = _complex_interleaved(w.dress_noise) if (w.dress_eps > 0 and w.dress_noise is not None) else None
+    keep += [pos, order, prod, noise]
+    cfg = Config()
+    cfg.n_sites = w.n_sites
+    cfg.d = w.d
+    cfg.chi = w.chi
+    cfg.krylov_dim = w.krylov_dim
+    cfg.precision = w.precision
+    cfg.c6 = w.c6
+    cfg.r_cut = w.r_cut
+    cfg.leak_ratio = w.leak_ratio
+    cfg.pos_xy = _dptr(pos)
+    cfg.leaf_order = _iptr(order)
+    cfg.init_product = _dptr(prod)
+    cfg.dress_eps = w.dress_eps
+    cfg.dress_noise = _dptr(noise) if noise is not None else C.POINTER(C.c_double)()
+    cfg.dress_noise_len = 0 if noise is None else noise.size // 2
+    return cfg
+
+
+def workspace_bytes(w) -> int:
+    keep: list = []
+    cfg = make_config(w, keep)
+    out = C.c_size_t(0)
+    rc = lib().ttn_workspace_query(C.byref(cfg), C.byref(out))
+    if rc != TTN_OK:
+        raise TTNError(rc, "workspace query failed")
+    return int(out.value)
+
+
+class TTN:
+    """One TTN state on the current CUDA (HIP) device."""
+
+    def __init__(self, w, device=None, stream=None):
+        import torch
+        self._keep: list = []
+        self.w = w
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        cfg = make_config(w, self._keep)
+        nbytes = C.c_size_t(0)
+        self._check(lib().ttn_workspace_query(C.byref(cfg), C.byref(nbytes)), None)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = C.c_void_p()
+        rc = lib().ttn_init(C.byref(cfg), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                            C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._check(rc, None)
+        self.h = h
+        self.set_pulses(w.seg_edges, w.omega, w.delta, w.events)
+
+    def _check(self, rc, h):
+        if rc < 0:
+            raise TTNError(rc, lib().ttn_last_error(h).decode())
+        return rc
+
+    def set_pulses(self, edges, omega, delta, events: Sequence = ()):
+        edges = np.ascontiguousarray(edges, dtype=np.float64)
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        de = np.ascontiguousarray(delta, dtype=np.float64)
+        steps = np.ascontiguousarray([e[0] for e in events], dtype=np.int32)
+        sites = np.ascontiguousarray([e[1] for e in events], dtype=np.int32)
+        us = (_complex_interleaved(np.stack([e[2] for e in events])) if len(events)
+              else np.zeros(2, np.float64))
+        self._pulses = (edges, om, de, steps, sites, us)
+        rc = lib().ttn_set_pulses(self.h, int(om.shape[1]) if om.ndim == 2 else 0, _dptr(edges), _dptr(om),
+                                  _dptr(de), len(events), _iptr(steps), _iptr(sites), _dptr(us))
+        self._check(rc, self.h)
+
+    def step(self, n_steps: int, dt: Optional[float] = None, stats: bool = False):
+        dt = self.w.dt if dt is None else dt
+        arr = (StepStats * max(1, n_steps))() if stats else None
+        rc = lib().ttn_tdvp_step(self.h, float(dt), int(n_steps), arr)
+        self._check(rc, self.h)
+        if stats:
+            return [dict(norm2=a.norm2, energy=a.energy, min_r_diag=a.min_r_diag,
+                         min_krylov=a.min_krylov) for a in arr[:n_steps]]
+        return None
+
+    def fidelity(self, target_sites=None):
+        ts = np.ascontiguousarray(self.w.target_sites if target_sites is None else target_sites,
+                                  dtype=np.int32)
+        F = C.c_double(0)
+        ov = np.zeros(2)
+        self._check(lib().ttn_fidelity(self.h, len(ts), _iptr(ts), C.byref(F), _dptr(ov)), self.h)
+        return F.value, complex(ov[0], ov[1])
+
+    def observables(self):
+        n2, e = C.c_double(0), C.c_double(0)
+        self._check(lib().ttn_observables(self.h, C.byref(n2), C.byref(e)), self.h)
+        return n2.value, e.value
+
+    def local_expectation(self, site: int, op) -> complex:
+        o = _complex_interleaved(op)
+        out = np.zeros(2)
+        self._check(lib().ttn_local_expectation(self.h, int(site), _dptr(o), _dptr(out)), self.h)
+        return complex(out[0], out[1])
+
+    def overlap(self, other: "TTN") -> complex:
+        out = np.zeros(2)
+        self._check(lib().ttn_overlap(self.h, other.h, _dptr(out)), self.h)
+        return complex(out[0], out[1])
+
+    def export_state(self) -> np.ndarray:
+        n = lib().ttn_export_state(self.h, None, 0)
+        buf = np.zeros(2 * n)
+        self._check(lib().ttn_export_state(self.h, _dptr(buf), n), self.h)
+        return buf.view(np.complex128)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ttn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,98 @@
+"""The C-ABI library loads and exports every symbol include/ttn.h declares;
+host-side validation paths (no device work) behave as documented."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2210_03763_amd import ttn as T
+from paper_2210_03763_amd import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ttn.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(ttn_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("ttn_init", "ttn_set_pulses", "ttn_tdvp_step", "ttn_fidelity", "ttn_backward"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(T.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_workspace_query_sizes():
+    w = W.config("c1-ent")
+    b = T.workspace_bytes(w)
+    assert 1 << 20 < b < 1 << 31
+    w3 = W.make_ghz_program(8, 8, 4, 128, 1, 0.005, seed=1, eps=0.0, precision=T.PREC_FP32)
+    b3 = T.workspace_bytes(w3)
+    # node tensors of the 8x8 d=4 chi=128 network alone are ~0.5 GB in FP64
+    assert b3 > 5e8
+
+
+@pytest.mark.parametrize("field,value", [("n_sites", 12), ("d", 5), ("chi", 0), ("krylov_dim", 17),
+                                         ("precision", 7)])
+def test_invalid_config_rejected(field, value):
+    w = W.config("c1-ent")
+    keep = []
+    cfg = T.make_config(w, keep)
+    setattr(cfg, field, value)
+    out = C.c_size_t(0)
+    assert T.lib().ttn_workspace_query(C.byref(cfg), C.byref(out)) == T.TTN_EINVAL
+
+
+def test_non_permutation_leaf_order_rejected():
+    w = W.config("c1-ent")
+    w = w.copy(leaf_order=np.zeros(16, np.int32))
+    with pytest.raises(T.TTNError) as e:
+        T.workspace_bytes(w)
+    assert e.value.code == T.TTN_EINVAL
+
+
+def test_null_handle_calls():
+    L = T.lib()
+    assert L.ttn_tdvp_step(None, 0.01, 1, None) == T.TTN_EINVAL
+    assert L.ttn_destroy(None) == T.TTN_EINVAL
+    assert L.ttn_backward(None, 1.0, None, None) == T.TTN_EINVAL
+
+
+def _validate(w, n_steps=1):
+    keep = []
+    cfg = T.make_config(w, keep)
+    msg = C.create_string_buffer(512)
+    L = T.lib()
+    L.ttn_validate_plan.restype = C.c_int
+    L.ttn_validate_plan.argtypes = [C.POINTER(T.Config), C.c_int32, C.c_char_p, C.c_int32]
+    rc = L.ttn_validate_plan(C.byref(cfg), n_steps, msg, 512)
+    return rc, msg.value.decode()
+
+
+@pytest.mark.parametrize("case", [
+    ("2x1 d3 chi9", lambda: W.make_random_drive(2, 1, 3, 9, 1, 0.01, 1, seed=1)),
+    ("2x2 d3 chi9", lambda: W.make_random_drive(2, 2, 3, 9, 1, 0.01, 1, seed=1)),
+    ("2x2 d4 chi16", lambda: W.make_random_drive(2, 2, 4, 16, 1, 0.01, 1, seed=1)),
+    ("2x4 d3 chi5", lambda: W.make_random_drive(4, 2, 3, 5, 1, 0.01, 1, seed=1)),
+    ("2x4 d3 chi81", lambda: W.make_random_drive(4, 2, 3, 81, 1, 0.01, 1, seed=1)),
+    ("4x4 d3 chi16", lambda: W.make_random_drive(4, 4, 3, 16, 1, 0.01, 1, seed=1)),
+    ("4x4 d4 chi12 fp32", lambda: W.make_random_drive(4, 4, 4, 12, 1, 0.01, 1, seed=1, precision=1)),
+    ("8x8 d3 chi64", lambda: W.make_ghz_program(8, 8, 3, 64, 1, 0.005, seed=1, eps=0.0)),
+    ("8x8 d4 chi128 fp32", lambda: W.make_ghz_program(8, 8, 4, 128, 1, 0.005, seed=1, eps=0.0,
+                                                     precision=1)),
+    ("8x8 d4 chi128 fp64", lambda: W.make_ghz_program(8, 8, 4, 128, 1, 0.005, seed=1, eps=0.0)),
+])
+def test_launch_plan_stays_in_bounds(case):
+    """Every GEMM operand and vector launch of init + steps + observables stays
+    inside its workspace allocation (checked on the host, no device)."""
+    name, mk = case
+    rc, msg = _validate(mk(), 2)
+    assert rc == T.TTN_OK, (name, msg)
