@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark: single-site TDVP steps/s of the 8x8, d=4, chi=128 Rydberg TTN
+(mixed precision: complex FP32 contractions, FP64 Krylov/QR) on one MI355X,
+with the H_eff contraction kernel's achieved TFLOP/s against the FP32 MFMA
+peak, the plain FP64 GPU path timed beside it, and the CPU oracle timed on a
+bounded sample.  Prints one JSON line.
+
+A step is one full TDVP step (S(dt/2) then S*(dt/2) over all 63 nodes and 62
+bonds, environment refresh and program events) of the GHZ-preparation
+program; inputs are synthetic and seeded and already resident on the device
+when the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TDVP steps/sec + H_eff MFMA util, 8x8 chi=128; mixed vs FP64 at 1e-5 fidel"
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+
+
+class KernelProf(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("gemm_f32", KernelProf), ("gemm_f64", KernelProf), ("heff", KernelProf),
+                ("matvecs", C.c_int64)]
+
+
+def heff_flops_per_step(w) -> float:
+    """Algorithmic real flops of all H_eff and K_eff matvecs of one step:
+    24 matvecs (two sweeps x Krylov dimension 12) per node and per bond, each
+    chi_L chi_R chi_P [chi_L (1 + s_L) + chi_R (1 + s_L + s_R) + chi_P (1 + s_L
+    + s_R)] complex multiply-adds at 8 real flops (parent-leg terms, and the
+    right-leg n_j products that only feed them, absent at the root)."""
+    N, d, chi = w.n_sites, w.d, w.chi
+    K = int(round(math.log2(N)))
+
+    def link(s):
+        return 1 if s >= N else min(chi, d ** min(s, 64), d ** min(N - s, 64))
+
+    m = w.krylov_dim
+    total = 0.0
+    for lvl in range(K):
+        nn = N >> (lvl + 1)
+        dc = d if lvl == 0 else link(1 << lvl)
+        dp = link(1 << (lvl + 1))
+        s = 1 << lvl
+        root = (lvl == K - 1)
+        node = dc * dc * dp * (dc * (1 + s) + dc * (1 + s + (0 if root else s))
+                               + (0 if root else dp * (1 + 2 * s)))
+        total += nn * 2 * m * node
+        if not root:   # bond above each node: (D, 1, D) tensor with 2s sites below
+            bond = dp * dp * (dp * (1 + 2 * s) + dp * (1 + 2 * s))
+            total += nn * 2 * m * bond
+    return 8.0 * total
+
+
+def cpu_baseline(w, flops_per_step, budget_s=30.0):
+    """The oracle (plain CPU FP64) timed on a bounded sample of the same
+    workload: environments of the first step are built (untimed), then the
+    oracle's H_eff matvec of the largest node is applied repeatedly for about
+    `budget_s` seconds.  steps/s = oracle matvec flop rate / H_eff flops per
+    step (an upper bound: the oracle's environment and QR work is left out)."""
+    import torch
+    from oracle import ttn_oracle as O
+    threads = torch.get_num_threads()
+    st = O.build(w)
+    st.set_time(torch.as_tensor(w.seg_edges), torch.as_tensor(w.omega), torch.as_tensor(w.delta),
+                0.5 * w.dt)
+    st.rebuild_up()
+    tr = st.tree
+    v = tr.children[tr.root][0]
+    st.build_down(v)
+    H = st.heff(v)
+    DL, DR, DP = tr.dims[v]
+    s = len(tr.child_sites(v, 0))
+    fl = 8.0 * DL * DR * DP * (DL * (1 + s) + DR * (1 + 2 * s) + DP * (1 + 2 * s))
+    x = st.T[v].clone()
+    n_done, t0 = 0, time.perf_counter()
+    while True:
+        x = H(x)
+        x = x / torch.linalg.vector_norm(x)
+        n_done += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n_done >= 64:
+            break
+    rate = n_done * fl / el
+    return {"value": rate / flops_per_step, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_done} oracle H_eff matvecs of the level-{tr.level[v]} node "
+                      f"({DL}x{DR}x{DP}, {fl / 1e9:.0f} GFLOP each) in {el:.1f} s on CPU "
+                      f"({rate / 1e9:.1f} GFLOP/s), scaled by {flops_per_step / 1e12:.1f} TFLOP of "
+                      f"H_eff/K_eff matvecs per step; environment/QR work not counted"}
+
+
+def run_gpu(w, steps, warmup, profile=True):
+    import torch
+    from paper_2210_03763_amd import ttn
+    L = ttn.lib()
+    L.ttn_profile_begin.argtypes = [C.c_void_p]
+    L.ttn_profile_end.argtypes = [C.c_void_p, C.POINTER(Profile)]
+    g = ttn.TTN(w, device="cuda:0")
+    if warmup:
+        g.step(warmup)
+    torch.cuda.synchronize()
+    if profile:
+        assert L.ttn_profile_begin(g.h) == 0
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = Profile()
+    if profile:
+        assert L.ttn_profile_end(g.h, C.byref(prof)) == 0
+    F, _ = g.fidelity()
+    n2, E = g.observables()
+    return g, (t1 - t0) * 1e3 / steps, prof, F, n2, E
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the TDVP sweep is sequential "
+              f"over tree nodes and this build has no multi-GPU path", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2210_03763_amd import ttn, workload as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    print(f"[bench] building workload {args.config}", file=sys.stderr, flush=True)
+    w = W.config(args.config)
+    fps = heff_flops_per_step(w)
+    print(f"[bench] mixed run: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr, flush=True)
+    gm, ms_mixed, prof, F_m, n2_m, E_m = run_gpu(w, args.steps, args.warmup)
+    print(f"[bench] mixed {ms_mixed:.1f} ms/step F={F_m:.12f}", file=sys.stderr, flush=True)
+    k = prof.gemm_f32 if w.precision == ttn.PREC_FP32 else prof.gemm_f64
+    dt = "fp32" if w.precision == ttn.PREC_FP32 else "fp64"
+    avg_ms = k.ms / max(1, k.launches)
+    achieved = (k.flops / 1e12) / (k.ms / 1e3) if k.ms > 0 else 0.0
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[dt], 4), "traffic": None,
+            "kernel": f"k_cgemm<{'float' if dt == 'fp32' else 'double'}> (H_eff/K_eff contraction stages)",
+            "launches": int(k.launches), "avg_launch_ms": round(avg_ms, 5),
+            "algorithmic_gflop_per_launch": round(k.flops / max(1, k.launches) / 1e9, 4),
+            "heff_share_of_kernel_flops": round(prof.heff.flops / max(1.0, k.flops), 4)}
+    out = {"metric": METRIC, "value": round(1e3 / ms_mixed, 4), "unit": "steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_mixed, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
+           "data": "synthetic (seeded GHZ-preparation pulse program, dressed product state)",
+           "config": {"workload": w.name, "lattice": f"{w.Lx}x{w.Ly}", "d": w.d, "chi": w.chi,
+                      "krylov_dim": w.krylov_dim, "dt": w.dt, "program_steps": w.n_steps,
+                      "precision": "complex FP32 contractions, FP64 Lanczos/QR/environments"
+                      if dt == "fp32" else "FP64",
+                      "heff_tflop_per_step": round(fps / 1e12, 3)},
+           "roofline": roof}
+    if not args.no_fp64 and w.precision == ttn.PREC_FP32:
+        w64 = w.copy(precision=ttn.PREC_FP64)
+        print(f"[bench] fp64 run: {args.steps} steps", file=sys.stderr, flush=True)
+        g64, ms64, prof64, F64, n2_64, E64 = run_gpu(w64, args.steps, args.warmup, profile=False)
+        ov = gm.overlap(g64)
+        out["fp64_path"] = {"ms_per_step": round(ms64, 3), "steps_per_s": round(1e3 / ms64, 4),
+                            "mixed_speedup": round(ms64 / ms_mixed, 3),
+                            "abs_dF": abs(F_m - F64), "state_infidelity_C": 1 - abs(ov) ** 2,
+                            "abs_dnorm2": abs(n2_m - n2_64), "abs_dE": abs(E_m - E64),
+                            "after_steps": args.steps + args.warmup}
+        g64.close()
+    gm.close()
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w.copy(precision=0), fps, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -149,6 +149,29 @@ int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len);
  * returns TTN_ENOTSUP. */
 int ttn_backward(ttn_handle* h, double dF, double* grad_omega, double* grad_delta);
 
+/* Device time of the contraction kernels inside a profiling window. */
+typedef struct {
+    int64_t launches;       /* kernel launches                                  */
+    double ms;              /* summed device time between events around them    */
+    double flops;           /* algorithmic real flops: 8 per complex multiply-add
+                               of the contraction (M N K per launch)            */
+} ttn_kernel_prof;
+
+typedef struct {
+    ttn_kernel_prof gemm_f32;   /* complex FP32 contraction kernel               */
+    ttn_kernel_prof gemm_f64;   /* complex FP64 contraction kernel               */
+    ttn_kernel_prof heff;       /* the subset that applies H_eff / K_eff         */
+    int64_t matvecs;            /* H_eff / K_eff applications                     */
+} ttn_profile;
+
+/* Opens a profiling window: from now on every contraction kernel launch is
+ * bracketed by HIP events on the handle's stream. */
+int ttn_profile_begin(ttn_handle* h);
+
+/* Closes the window (synchronises the stream) and sums the event times and
+ * algorithmic flops per kernel class. */
+int ttn_profile_end(ttn_handle* h, ttn_profile* out);
+
 /* Checks the launch plan of a configuration without a device: walks
  * initialisation, n_steps TDVP steps of a one-segment program with a gate on
  * every site, the fidelity, a local expectation and a self overlap, and

@@ -319,7 +319,9 @@ class OracleTTN:
                 e = torch.zeros(DL * DR, dtype=CDT)
                 e[k] = 1.0
                 for c in cols:
-                    e = e - torch.vdot(c, e) * c
+                    coef = torch.vdot(c, e)
+                    if coef != 0:
+                        e = e - coef * c
                 nrm = torch.linalg.vector_norm(e)
                 if float(nrm) > COMPLETION_TOL:
                     cols.append(e / nrm)

@@ -109,6 +109,18 @@ struct ttn_handle {
     // workspace regions for launch extent checks (sorted by address)
     std::vector<Region> regions;
     bool dry = false;
+    // profiling window: event pairs around GEMM kernel launches
+    bool prof = false;
+    bool in_heff = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct ProfRec {
+        int ev;          // index of the begin event; end event is ev + 1
+        int prec;        // 0 fp64, 1 fp32
+        double flops;    // algorithmic real flops (8 per complex multiply-add)
+        bool heff;
+    };
+    std::vector<ProfRec> prof_recs;
+    int64_t prof_matvecs = 0;
 };
 
 namespace {
@@ -252,7 +264,20 @@ struct Ctx {
     const int* skip;
     void run(const Gemm<R>& g) {
         char why[256];
-        if (!cgemm<R>(g, h->gs, h->stream, why, sizeof(why)))
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->prof && !h->dry && g.M > 0 && g.N > 0) {
+            const int idx = (int)h->prof_recs.size() * 2;
+            while ((int)h->ev_pool.size() < idx + 2) {
+                hipEvent_t e;
+                HIPCHECK(hipEventCreate(&e));
+                h->ev_pool.push_back(e);
+            }
+            e0 = h->ev_pool[idx];
+            e1 = h->ev_pool[idx + 1];
+            const double fl = 8.0 * g.M * g.N * (double)g.Kin * g.Kout * (double)g.B1 * g.B2;
+            h->prof_recs.push_back({idx, sizeof(R) == 4 ? 1 : 0, fl, h->in_heff});
+        }
+        if (!cgemm<R>(g, h->gs, h->stream, why, sizeof(why), e0, e1))
             throw StatusError{TTN_EINVAL, std::string("launch extent check failed: ") + why};
     }
 };
@@ -622,6 +647,14 @@ void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
 void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, const int* skip,
                    bool force_fp64 = false) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
+    struct HeffMark {
+        ttn_handle* h;
+        explicit HeffMark(ttn_handle* hh) : h(hh) {
+            h->in_heff = true;
+            if (h->prof) h->prof_matvecs += 1;
+        }
+        ~HeffMark() { h->in_heff = false; }
+    } mark(h);
     if (h->prec == TTN_PREC_FP32 && !force_fp64) {
         Ctx<float> c{h, skip};
         convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
@@ -679,7 +712,7 @@ void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, doubl
     chk(h, h->Linv, 2 * (int64_t)D * D, "Linv");
     chk(h, h->R1, 2 * (int64_t)D * D, "R1");
     chk(h, Rout, 2 * (int64_t)D * D, "R out");
-    if (D > 128) chk(h, h->cholwork, (int64_t)D * (D + 1), "cholesky work");
+    if (D > 128) chk(h, h->cholwork, (int64_t)D * (D + 1) + 2 * D, "cholesky work");
     leg_gram(c, leg, Tv, Tv, 0, h->G, 0, DL, DR, DP, 1);
     chol_inv(h->G, D, h->Linv, h->R1, nullptr, h->cholwork, h->st, h->stream);
     leg_apply<double>(c, leg, h->Linv, 0, Tv, 0, h->Qtmp, 0, DL, DR, DP, 1, 0, true, false);
@@ -1035,14 +1068,26 @@ void initial_tensors(ttn_handle* h, const ttn_config* cfg) {
         cr.push_back(c0r);
         ci.push_back(c0i);
         for (int64_t k = 0; k < LR && (int)cr.size() < DP; ++k) {
+            // candidate e_k; modified Gram-Schmidt against the accepted columns.
+            // While e is still the unit vector, <c_q, e> = conj(c_q[k]) and a
+            // zero coefficient leaves e unchanged, so most columns of large
+            // nodes cost O(1).
             std::vector<double> er(LR, 0.0), ei(LR, 0.0);
             er[k] = 1.0;
+            bool unit = true;
             for (size_t q = 0; q < cr.size(); ++q) {
                 double dr = 0, di = 0;   // <c_q, e>
-                for (int64_t i = 0; i < LR; ++i) {
-                    dr += cr[q][i] * er[i] + ci[q][i] * ei[i];
-                    di += cr[q][i] * ei[i] - ci[q][i] * er[i];
+                if (unit) {
+                    dr = cr[q][k];
+                    di = -ci[q][k];
+                } else {
+                    for (int64_t i = 0; i < LR; ++i) {
+                        dr += cr[q][i] * er[i] + ci[q][i] * ei[i];
+                        di += cr[q][i] * ei[i] - ci[q][i] * er[i];
+                    }
                 }
+                if (dr == 0.0 && di == 0.0) continue;
+                unit = false;
                 for (int64_t i = 0; i < LR; ++i) {
                     er[i] -= dr * cr[q][i] - di * ci[q][i];
                     ei[i] -= dr * ci[q][i] + di * cr[q][i];
@@ -1479,6 +1524,44 @@ int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len) {
     }
 }
 
+int ttn_profile_begin(ttn_handle* h) {
+    if (!h) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    h->prof = true;
+    h->prof_recs.clear();
+    h->prof_matvecs = 0;
+    return TTN_OK;
+}
+
+int ttn_profile_end(ttn_handle* h, ttn_profile* out) {
+    if (!h || !out) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        sync(h);
+        std::memset(out, 0, sizeof(*out));
+        for (const auto& r : h->prof_recs) {
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, h->ev_pool[r.ev], h->ev_pool[r.ev + 1]));
+            ttn_kernel_prof& k = r.prec ? out->gemm_f32 : out->gemm_f64;
+            k.launches += 1;
+            k.ms += ms;
+            k.flops += r.flops;
+            if (r.heff) {
+                out->heff.launches += 1;
+                out->heff.ms += ms;
+                out->heff.flops += r.flops;
+            }
+        }
+        out->matvecs = h->prof_matvecs;
+        h->prof = false;
+        h->prof_recs.clear();
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        h->prof = false;
+        return fail(h, e);
+    }
+}
+
 int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t msg_len) {
     ttn_handle* h = nullptr;
     auto report = [&](const std::string& m) {
@@ -1553,6 +1636,7 @@ int ttn_destroy(ttn_handle* h) {
     if (!h) return TTN_EINVAL;
     if (!h->dry) {
         if (h->stream) (void)hipStreamSynchronize(h->stream);
+        for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
         if (h->d_omega) (void)hipFree(h->d_omega);
         if (h->d_delta) (void)hipFree(h->d_delta);
         if (h->d_evU) (void)hipFree(h->d_evU);

@@ -215,7 +215,8 @@ inline bool inside(const GemmScratch& ws, const void* base, int64_t max_off, int
 bool g_dry_run = false;
 
 template <typename R>
-bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen) {
+bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen, hipEvent_t ev0,
+           hipEvent_t ev1) {
     if (g.M <= 0 || g.N <= 0 || g.B1 * g.B2 <= 0) return true;
     {
         const int64_t km = g.Kin > 0 ? g.Kin - 1 : 0, ko = g.Kout > 0 ? g.Kout - 1 : 0;
@@ -261,8 +262,10 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
     const int a_mfast = (g.sam == 1 || g.sak != 1) ? 1 : 0;
     const int b_nfast = (g.sbn == 1 || g.sbk != 1) ? 1 : 0;
     const int64_t blocks = tiles * splits;
+    if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_cgemm<R, BM, BN, BK>), dim3((unsigned)blocks), dim3(GEMM_THREADS), 0, s, g,
                        tilesM, tilesN, splits, kchunk, (R*)ws.partial, a_mfast, b_nfast);
+    if (ev1) (void)hipEventRecord(ev1, s);
     if (splits > 1) {
         const int64_t total = (int64_t)g.M * g.N * nbatch;
         const int nb = (int)std::min<int64_t>((total + 255) / 256, 4096);
@@ -272,8 +275,10 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
     return true;
 }
 
-template bool cgemm<double>(const Gemm<double>&, const GemmScratch&, hipStream_t, char*, int);
-template bool cgemm<float>(const Gemm<float>&, const GemmScratch&, hipStream_t, char*, int);
+template bool cgemm<double>(const Gemm<double>&, const GemmScratch&, hipStream_t, char*, int, hipEvent_t,
+                            hipEvent_t);
+template bool cgemm<float>(const Gemm<float>&, const GemmScratch&, hipStream_t, char*, int, hipEvent_t,
+                           hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // reductions for Lanczos
@@ -368,13 +373,19 @@ __global__ void k_multidot_partial(const double* V, int kcount, const double* w,
 __global__ void k_multidot_final(const double* partial, int nb, int kcount, LanczosDev* lz,
                                  int alpha_index) {
     if (lz->done) return;
-    const int k = threadIdx.x;
-    if (k < kcount) {
-        double re = 0, im = 0;
-        for (int b = 0; b < nb; ++b) {
-            re += partial[(b * KRYLOV_MAX + k) * 2];
-            im += partial[(b * KRYLOV_MAX + k) * 2 + 1];
-        }
+    // wave k sums the partials of vector k (lanes stride over blocks)
+    const int k = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (k >= kcount) return;
+    double re = 0, im = 0;
+    for (int b = lane; b < nb; b += 64) {
+        re += partial[(b * KRYLOV_MAX + k) * 2];
+        im += partial[(b * KRYLOV_MAX + k) * 2 + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_down(re, o, 64);
+        im += __shfl_down(im, o, 64);
+    }
+    if (lane == 0) {
         lz->c[2 * k] = re;
         lz->c[2 * k + 1] = im;
         if (k == alpha_index) {
@@ -419,60 +430,83 @@ __global__ void k_lz_beta(const double* partial, int nb, LanczosDev* lz, int j, 
     }
 }
 
-// exp(-i tau T) e_1 for the real symmetric tridiagonal T (alpha, beta) of
-// size m_eff, by cyclic Jacobi rotations: T = U diag(lambda) U^T.
+// y = exp(-i tau T) e_1 for the real symmetric tridiagonal T (alpha, beta)
+// of size m_eff: the Taylor series of exp(B/s), B = -i tau T, applied s times
+// to the vector, with s chosen so that ||B/s||_1 <= 1/4 (terms are summed
+// until they stop changing the result in double precision).
 __global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
     if (threadIdx.x != 0 || lz->zero) return;
     const int m = lz->m_eff;
-    double a[KRYLOV_MAX][KRYLOV_MAX], u[KRYLOV_MAX][KRYLOV_MAX];
-    for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) {
-            a[i][j] = 0;
-            u[i][j] = (i == j) ? 1.0 : 0.0;
-        }
-    for (int i = 0; i < m; ++i) a[i][i] = lz->alpha[i];
-    for (int i = 0; i + 1 < m; ++i) a[i][i + 1] = a[i + 1][i] = lz->beta[i];
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0, dg = 0;
-        for (int p = 0; p < m; ++p) {
-            dg += a[p][p] * a[p][p];
-            for (int q = p + 1; q < m; ++q) off += a[p][q] * a[p][q];
-        }
-        if (off <= 1e-34 * dg || off == 0.0) break;
-        for (int p = 0; p < m; ++p)
-            for (int q = p + 1; q < m; ++q) {
-                const double apq = a[p][q];
-                if (apq == 0.0) continue;
-                const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < m; ++k) {   // columns p, q
-                    const double akp = a[k][p], akq = a[k][q];
-                    a[k][p] = c * akp - s * akq;
-                    a[k][q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < m; ++k) {   // rows p, q
-                    const double apk = a[p][k], aqk = a[q][k];
-                    a[p][k] = c * apk - s * aqk;
-                    a[q][k] = s * apk + c * aqk;
-                }
-                for (int k = 0; k < m; ++k) {
-                    const double ukp = u[k][p], ukq = u[k][q];
-                    u[k][p] = c * ukp - s * ukq;
-                    u[k][q] = s * ukp + c * ukq;
-                }
-            }
+    double al[KRYLOV_MAX], be[KRYLOV_MAX];
+#pragma unroll
+    for (int i = 0; i < KRYLOV_MAX; ++i) {
+        al[i] = i < m ? lz->alpha[i] : 0.0;
+        be[i] = i + 1 < m ? lz->beta[i] : 0.0;   // T[i][i+1] = T[i+1][i] = beta[i]
     }
-    for (int i = 0; i < m; ++i) {
-        double yr = 0, yi = 0;
-        for (int k = 0; k < m; ++k) {
-            const double ph = -tau * a[k][k];
-            const double w = u[i][k] * u[0][k];
-            yr += w * cos(ph);
-            yi += w * sin(ph);
+    double nrm = 0;
+#pragma unroll
+    for (int i = 0; i < KRYLOV_MAX; ++i) {
+        const double c = fabs(al[i]) + fabs(be[i]) + (i > 0 ? fabs(be[i - 1]) : 0.0);
+        nrm = c > nrm ? c : nrm;
+    }
+    nrm *= fabs(tau);
+    int ns = (int)ceil(nrm / 0.25);
+    if (ns < 1) ns = 1;
+    const double h = tau / ns;
+    double vr[KRYLOV_MAX], vi[KRYLOV_MAX];
+#pragma unroll
+    for (int i = 0; i < KRYLOV_MAX; ++i) {
+        vr[i] = i == 0 ? 1.0 : 0.0;
+        vi[i] = 0.0;
+    }
+    for (int rep = 0; rep < ns; ++rep) {
+        double tr[KRYLOV_MAX], ti[KRYLOV_MAX], wr[KRYLOV_MAX], wi[KRYLOV_MAX];
+#pragma unroll
+        for (int i = 0; i < KRYLOV_MAX; ++i) {
+            tr[i] = wr[i] = vr[i];
+            ti[i] = wi[i] = vi[i];
         }
-        lz->y[2 * i] = yr;
-        lz->y[2 * i + 1] = yi;
+        for (int k = 1; k <= 40; ++k) {
+            // term <- (-i h T term) / k :  re' = h (T ti) / k,  im' = -h (T tr) / k
+            double nr[KRYLOV_MAX], ni[KRYLOV_MAX];
+            const double f = h / k;
+            double tmax = 0, wmax = 0;
+#pragma unroll
+            for (int i = 0; i < KRYLOV_MAX; ++i) {
+                double sr = al[i] * tr[i], si = al[i] * ti[i];
+                if (i > 0) {
+                    sr += be[i - 1] * tr[i - 1];
+                    si += be[i - 1] * ti[i - 1];
+                }
+                if (i + 1 < KRYLOV_MAX) {
+                    sr += be[i] * tr[i + 1];
+                    si += be[i] * ti[i + 1];
+                }
+                nr[i] = f * si;
+                ni[i] = -f * sr;
+            }
+#pragma unroll
+            for (int i = 0; i < KRYLOV_MAX; ++i) {
+                tr[i] = nr[i];
+                ti[i] = ni[i];
+                wr[i] += tr[i];
+                wi[i] += ti[i];
+                const double ta = fabs(tr[i]) + fabs(ti[i]), wa = fabs(wr[i]) + fabs(wi[i]);
+                tmax = ta > tmax ? ta : tmax;
+                wmax = wa > wmax ? wa : wmax;
+            }
+            if (tmax <= 1e-18 * wmax) break;
+        }
+#pragma unroll
+        for (int i = 0; i < KRYLOV_MAX; ++i) {
+            vr[i] = wr[i];
+            vi[i] = wi[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < KRYLOV_MAX; ++i) {
+        lz->y[2 * i] = i < m ? vr[i] : 0.0;
+        lz->y[2 * i + 1] = i < m ? vi[i] : 0.0;
     }
     atomicMin(&st->min_krylov, m);
 }
@@ -525,7 +559,7 @@ void lz_project(const double* V, int kcount, const double* w, int64_t n, double*
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_multidot_partial, dim3(nb), dim3(RED_THREADS), 0, s, V, kcount, w, n,
                        partial, lz);
-    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64), 0, s, partial, nb, kcount, lz,
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64 * kcount), 0, s, partial, nb, kcount, lz,
                        alpha_index);
 }
 
@@ -631,19 +665,25 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int 
                                                            double* work, StepDev* st) {
     __shared__ double sLre[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) / 2 : 1];
     __shared__ double sLim[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) / 2 : 1];
+    __shared__ double col_re[LDS ? CHOL_LDS_MAX : 1], col_im[LDS ? CHOL_LDS_MAX : 1];
     __shared__ int s_bad;
     const int64_t np = (int64_t)D * (D + 1) / 2;
     double* Lre = LDS ? sLre : work;
     double* Lim = LDS ? sLim : work + np;
+    double* cr = LDS ? col_re : work + 2 * np;
+    double* ci = LDS ? col_im : work + 2 * np + D;
     const int tid = threadIdx.x;
+    const int tx = tid % 32, ty = tid / 32;      // 32 x 16 thread grid
+    constexpr int TY = CHOL_THREADS / 32;
     const int64_t DD = (int64_t)D * D;
     if (tid == 0) s_bad = 0;
-    for (int j = 0; j < D; ++j)
-        for (int i = j + tid; i < D; i += CHOL_THREADS) {
+    for (int j = ty; j < D; j += TY)
+        for (int i = j + tx; i < D; i += 32) {
             Lre[pidx(i, j, D)] = G[i + (int64_t)D * j];
             Lim[pidx(i, j, D)] = G[DD + i + (int64_t)D * j];
         }
     __syncthreads();
+    // right-looking Cholesky G = L L^H (lower, packed)
     for (int j = 0; j < D; ++j) {
         const int64_t jj = pidx(j, j, D);
         if (tid == 0) {
@@ -655,51 +695,26 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int 
         __syncthreads();
         const double dinv = 1.0 / Lre[jj];
         for (int i = j + 1 + tid; i < D; i += CHOL_THREADS) {
-            Lre[pidx(i, j, D)] *= dinv;
-            Lim[pidx(i, j, D)] *= dinv;
+            const int64_t q = pidx(i, j, D);
+            Lre[q] *= dinv;
+            Lim[q] *= dinv;
+            cr[i] = Lre[q];
+            ci[i] = Lim[q];
         }
         __syncthreads();
-        const int rn = D - j - 1;
-        for (int e = tid; e < rn * rn; e += CHOL_THREADS) {
-            const int ii = e % rn, kk = e / rn;
-            if (ii < kk) continue;
-            const int i = j + 1 + ii, k = j + 1 + kk;
-            const double ar = Lre[pidx(i, j, D)], ai = Lim[pidx(i, j, D)];
-            const double br = Lre[pidx(k, j, D)], bi = Lim[pidx(k, j, D)];
-            // L[i][k] -= L[i][j] * conj(L[k][j])
-            Lre[pidx(i, k, D)] -= ar * br + ai * bi;
-            Lim[pidx(i, k, D)] -= ai * br - ar * bi;
-        }
-        __syncthreads();
-    }
-    // X = L^{-1}, lower triangular, row by row: X[i][j] = -(sum_{k=j}^{i-1} L[i][k] X[k][j]) / L[i][i]
-    double* Xr = Linv;
-    double* Xi = Linv + DD;
-    for (int e = tid; e < DD; e += CHOL_THREADS) {
-        Xr[e] = 0.0;
-        Xi[e] = 0.0;
-    }
-    __syncthreads();
-    for (int i = 0; i < D; ++i) {
-        const double lii = Lre[pidx(i, i, D)];
-        for (int j = tid; j <= i; j += CHOL_THREADS) {
-            if (j == i) {
-                Xr[i + (int64_t)D * i] = 1.0 / lii;
-                continue;
+        // L[i][k] -= L[i][j] conj(L[k][j]) for j < k <= i
+        for (int k = j + 1 + ty; k < D; k += TY) {
+            const double br = cr[k], bi = ci[k];
+            const int64_t base = pidx(k, k, D) - k;
+            for (int i = k + tx; i < D; i += 32) {
+                const double ar = cr[i], ai = ci[i];
+                Lre[base + i] -= ar * br + ai * bi;
+                Lim[base + i] -= ai * br - ar * bi;
             }
-            double sr = 0, si = 0;
-            for (int k = j; k < i; ++k) {
-                const double lr = Lre[pidx(i, k, D)], li = Lim[pidx(i, k, D)];
-                const double xr = Xr[k + (int64_t)D * j], xi = Xi[k + (int64_t)D * j];
-                sr += lr * xr - li * xi;
-                si += lr * xi + li * xr;
-            }
-            Xr[i + (int64_t)D * j] = -sr / lii;
-            Xi[i + (int64_t)D * j] = -si / lii;
         }
         __syncthreads();
     }
-    // R = L^H (upper), optionally times Rprev (upper): R[k][a] = sum_{j=k}^{a} conj(L[j][k]) Rprev[j][a]
+    // R = L^H, or L^H Rprev:  R[k][a] = sum_{j=k}^{a} conj(L[j][k]) Rprev[j][a]
     for (int e = tid; e < DD; e += CHOL_THREADS) {
         const int k = (int)(e % D), a = (int)(e / D);
         double rr = 0, ri = 0;
@@ -708,8 +723,9 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int 
                 rr = Lre[pidx(a, k, D)];
                 ri = -Lim[pidx(a, k, D)];
             } else {
+                const int64_t base = pidx(k, k, D) - k;
                 for (int j = k; j <= a; ++j) {
-                    const double lr = Lre[pidx(j, k, D)], li = -Lim[pidx(j, k, D)];
+                    const double lr = Lre[base + j], li = -Lim[base + j];
                     const double pr = Rprev[j + (int64_t)D * a], pi = Rprev[DD + j + (int64_t)D * a];
                     rr += lr * pr - li * pi;
                     ri += lr * pi + li * pr;
@@ -728,6 +744,52 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int 
         }
         if (s_bad || !(mn == mn)) atomicExch(&st->bad, 1);
         if (mn > 0) atomicMin(&st->min_rdiag_bits, (unsigned long long)__double_as_longlong(mn));
+    }
+    // in-place inverse X = L^{-1} by elimination on the identity:
+    // step k: row k of X scaled by 1/L[k][k]; then rows i > k lose L[i][k] X[k][:]
+    for (int k = 0; k < D; ++k) {
+        const int64_t kk = pidx(k, k, D);
+        const double d = 1.0 / Lre[kk];   // (k, k) is not written by step k-1
+        __syncthreads();
+        for (int j = tid; j < k; j += CHOL_THREADS) {
+            const int64_t q = pidx(k, j, D);
+            Lre[q] *= d;
+            Lim[q] *= d;
+        }
+        for (int i = k + 1 + tid; i < D; i += CHOL_THREADS) {
+            const int64_t q = pidx(i, k, D);
+            cr[i] = Lre[q];
+            ci[i] = Lim[q];
+        }
+        if (tid == 0) {
+            Lre[kk] = d;
+            Lim[kk] = 0.0;
+        }
+        __syncthreads();
+        // X[i][j] = (j == k ? 0 : X[i][j]) - L[i][k] X[k][j]   for i > k, j <= k
+        for (int j = ty; j <= k; j += TY) {
+            const int64_t qk = pidx(k, j, D);
+            const double xr = Lre[qk], xi = Lim[qk];
+            const int64_t base = pidx(j, j, D) - j;
+            for (int i = k + 1 + tx; i < D; i += 32) {
+                const double lr = cr[i], li = ci[i];
+                const double or_ = (j == k) ? 0.0 : Lre[base + i];
+                const double oi = (j == k) ? 0.0 : Lim[base + i];
+                Lre[base + i] = or_ - (lr * xr - li * xi);
+                Lim[base + i] = oi - (lr * xi + li * xr);
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < DD; e += CHOL_THREADS) {
+        const int i = (int)(e % D), j = (int)(e / D);
+        double xr = 0, xi = 0;
+        if (i >= j) {
+            xr = Lre[pidx(i, j, D)];
+            xi = Lim[pidx(i, j, D)];
+        }
+        Linv[e] = xr;
+        Linv[DD + e] = xi;
     }
 }
 

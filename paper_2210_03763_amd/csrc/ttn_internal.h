@@ -52,7 +52,8 @@ struct GemmScratch {
 // Returns false (and launches nothing) when an operand would leave its
 // region; `why` receives a description.
 template <typename R>
-bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen);
+bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen,
+           hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
 // When set, launchers validate but enqueue nothing (plan checking without a
 // device).
