@@ -149,6 +149,25 @@ int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len);
  * returns TTN_ENOTSUP. */
 int ttn_backward(ttn_handle* h, double dF, double* grad_omega, double* grad_delta);
 
+/* The tensor-product-operator contraction on one leg of node tensors
+ * (Sec. "Tensor network simulations": each term of the Hamiltonian acts on
+ * a node through its environment operators), on caller device memory:
+ *   sum_ops == 0:  y_k = Op_k (x) leg  x_k   for k < n_ops
+ *   sum_ops != 0:  y   = sum_k Op_k (x) leg  x_k
+ * where (Op (x) leg x)[.., a, ..] = sum_b Op[a, b] x[.., b, ..], leg 0/1/2 =
+ * left/right/parent of a (DL, DR, DP) tensor with the left index fastest.
+ * Every array is planar complex (all real parts, then all imaginary parts)
+ * in FP64 or FP32 (precision); Op_k are D x D column-major (D = dimension
+ * of the leg), stored one after another (2 D^2 reals each); x_k likewise
+ * (2 DL DR DP reals each) when x_per_op != 0, otherwise one x is shared
+ * (sum_ops requires x_per_op).  accumulate != 0 adds into y.  Enqueued on
+ * hip_stream and synchronised before returning; the arrays are borrowed.
+ * Allocates and frees its own split-K scratch.  TTN_EINVAL for bad sizes;
+ * ttn_last_error(NULL) gives the text. */
+int ttn_leg_contract(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int32_t DP, int32_t n_ops,
+                     const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y, int32_t sum_ops,
+                     int32_t accumulate, void* hip_stream);
+
 /* Device time of the contraction kernels inside a profiling window. */
 typedef struct {
     int64_t launches;       /* kernel launches                                  */

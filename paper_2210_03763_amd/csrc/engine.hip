@@ -1524,6 +1524,61 @@ int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len) {
     }
 }
 
+int ttn_leg_contract(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int32_t DP, int32_t n_ops,
+                     const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y, int32_t sum_ops,
+                     int32_t accumulate, void* hip_stream) {
+    try {
+        if (precision != TTN_PREC_FP64 && precision != TTN_PREC_FP32) return TTN_EINVAL;
+        if (leg < 0 || leg > 2 || DL < 1 || DR < 1 || DP < 1 || n_ops < 1 || !d_ops || !d_x || !d_y)
+            return TTN_EINVAL;
+        if (sum_ops && !x_per_op) return TTN_EINVAL;
+        const int D = leg == 0 ? DL : (leg == 1 ? DR : DP);
+        const int64_t n = (int64_t)DL * DR * DP, D2 = (int64_t)D * D;
+        const size_t esz = precision == TTN_PREC_FP32 ? 4 : 8;
+        ttn_handle h;
+        h.stream = (hipStream_t)hip_stream;
+        // operand regions come from the argument sizes; split-K scratch is
+        // allocated here for this call
+        const int nx = x_per_op ? n_ops : 1, ny = sum_ops ? 1 : n_ops;
+        h.regions.push_back(Region{(uintptr_t)d_ops, (uintptr_t)d_ops + 2 * D2 * n_ops * esz});
+        h.regions.push_back(Region{(uintptr_t)d_x, (uintptr_t)d_x + 2 * n * nx * esz});
+        h.regions.push_back(Region{(uintptr_t)d_y, (uintptr_t)d_y + 2 * n * ny * esz});
+        h.gs.bytes = (int64_t)64 << 20;
+        HIPCHECK(hipMalloc(&h.gs.partial, h.gs.bytes));
+        sort_regions(&h);
+        try {
+            if (precision == TTN_PREC_FP32) {
+                Ctx<float> c{&h, nullptr};
+                if (sum_ops)
+                    leg_apply_sum<float>(c, leg, (const float*)d_ops, 2 * D2, (const float*)d_x, 2 * n, (float*)d_y,
+                                         DL, DR, DP, n_ops, accumulate ? 1 : 0);
+                else
+                    leg_apply<float>(c, leg, (const float*)d_ops, 2 * D2, (const float*)d_x, x_per_op ? 2 * n : 0,
+                                     (float*)d_y, 2 * n, DL, DR, DP, n_ops, accumulate ? 1 : 0);
+            } else {
+                Ctx<double> c{&h, nullptr};
+                if (sum_ops)
+                    leg_apply_sum<double>(c, leg, (const double*)d_ops, 2 * D2, (const double*)d_x, 2 * n,
+                                          (double*)d_y, DL, DR, DP, n_ops, accumulate ? 1 : 0);
+                else
+                    leg_apply<double>(c, leg, (const double*)d_ops, 2 * D2, (const double*)d_x, x_per_op ? 2 * n : 0,
+                                      (double*)d_y, 2 * n, DL, DR, DP, n_ops, accumulate ? 1 : 0);
+            }
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipStreamSynchronize(h.stream));
+        } catch (...) {
+            (void)hipStreamSynchronize(h.stream);
+            (void)hipFree(h.gs.partial);
+            throw;
+        }
+        HIPCHECK(hipFree(h.gs.partial));
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        g_init_error = e.msg;
+        return e.code;
+    }
+}
+
 int ttn_profile_begin(ttn_handle* h) {
     if (!h) return TTN_EINVAL;
     if (h->poisoned) return TTN_ESTATE;
