@@ -21,7 +21,7 @@ namespace {
 
 constexpr double LANCZOS_TOL = 1e-12;     // beta_{j+1} <= tol (|alpha_j| + beta_j)
 constexpr double COMPLETION_TOL = 1e-8;   // Gram-Schmidt acceptance for initial isometries
-constexpr int RED_BLOCKS = 256;
+constexpr int RED_BLOCKS = 2048;
 
 struct StatusError {
     int code;
@@ -83,8 +83,8 @@ struct ttn_handle {
     double *X = nullptr, *W = nullptr, *Vk = nullptr, *Qtmp = nullptr, *Ttmp = nullptr;
     float *Xf = nullptr, *Yf = nullptr;
     double *Bstk = nullptr, *Astk = nullptr;
-    float *Lf = nullptr, *Rf = nullptr, *Bf = nullptr, *Wf = nullptr;
-    double *G = nullptr, *Linv = nullptr, *R1 = nullptr, *Rq = nullptr, *Cb = nullptr,
+    float *Lf = nullptr, *Rf = nullptr, *Bf = nullptr, *Wf = nullptr, *Ef = nullptr;
+    double *G = nullptr, *Linv = nullptr, *R1 = nullptr, *R2 = nullptr, *Rq = nullptr, *Cb = nullptr,
            *cholwork = nullptr;
     double* red = nullptr;
     LanczosDev *lz = nullptr, *lz_obs = nullptr;
@@ -229,15 +229,17 @@ void plan(ttn_handle* h, Bump& b) {
         h->Rf = b.take<float>(2 * smax * D2);
         h->Bf = b.take<float>(2 * smax * D2);
         h->Wf = b.take<float>(2 * smax * D2);
+        h->Ef = b.take<float>(2 * h->env_max);
     }
     h->Bstk = b.take<double>(2 * smax * D2);
     h->Astk = b.take<double>(2 * smax * D2);
     h->G = b.take<double>(2 * D2);
     h->Linv = b.take<double>(2 * D2);
     h->R1 = b.take<double>(2 * D2);
+    h->R2 = b.take<double>(2 * D2);
     h->Rq = b.take<double>(2 * D2);
     h->Cb = b.take<double>(2 * D2);
-    h->cholwork = b.take<double>(2 * D2 + 64);
+    h->cholwork = b.take<double>(2 * D2 + 2 * (int64_t)h->Dmax * 16 + 64);
     h->red = b.take<double>((int64_t)RED_BLOCKS * KRYLOV_MAX * 2 + 64);
     h->lz = b.take<LanczosDev>(1);
     h->lz_obs = b.take<LanczosDev>(1);
@@ -474,10 +476,11 @@ void leg_apply_sum(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int6
 
 // E_k[a, b] = sum over the other legs of conj(Q[.., a, ..]) X_k[.., b, ..]
 // for nx tensors X_k (stride sx); outputs D x D column-major (stride se).
-void leg_gram(Ctx<double>& c, int leg, const double* Q, const double* X, int64_t sx, double* E,
-              int64_t se, int DL, int DR, int DP, int nx) {
+template <typename R>
+void leg_gram(Ctx<R>& c, int leg, const R* Q, const R* X, int64_t sx, R* E, int64_t se, int DL, int DR, int DP,
+              int nx) {
     const int64_t n = (int64_t)DL * DR * DP;
-    Gemm<double> g;
+    Gemm<R> g;
     g.skip = c.skip;
     g.conjA = true;
     g.A = Q;
@@ -687,12 +690,11 @@ void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
     for (int j = 0; j < h->m; ++j) {
         double* vj = h->Vk + 2 * n * j;
         apply_op_prec(h, o, vj, h->W, &lz->done);
+        // classical Gram-Schmidt, two passes: the first projection also gives alpha_j
         lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s);
         if (j == h->m - 1) break;
-        lz_subtract(h->Vk, j + 1, h->W, n, lz, s);
-        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, -1, s);
-        lz_subtract(h->Vk, j + 1, h->W, n, lz, s);
-        lz_next(h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s);
+        lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s);
+        lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s);
     }
     lz_expm(lz, tau, h->st, s);
     lz_combine(h->Vk, n, x, lz, s);
@@ -711,14 +713,32 @@ void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, doubl
     chk(h, h->G, 2 * (int64_t)D * D, "gram");
     chk(h, h->Linv, 2 * (int64_t)D * D, "Linv");
     chk(h, h->R1, 2 * (int64_t)D * D, "R1");
+    chk(h, h->R2, 2 * (int64_t)D * D, "R2");
     chk(h, Rout, 2 * (int64_t)D * D, "R out");
-    if (D > 128) chk(h, h->cholwork, (int64_t)D * (D + 1) + 2 * D, "cholesky work");
+    chk(h, h->cholwork, (int64_t)D * (D + 1) + 2 * (int64_t)D * 16, "cholesky work");
     leg_gram(c, leg, Tv, Tv, 0, h->G, 0, DL, DR, DP, 1);
     chol_inv(h->G, D, h->Linv, h->R1, nullptr, h->cholwork, h->st, h->stream);
     leg_apply<double>(c, leg, h->Linv, 0, Tv, 0, h->Qtmp, 0, DL, DR, DP, 1, 0, true, false);
     leg_gram(c, leg, h->Qtmp, h->Qtmp, 0, h->G, 0, DL, DR, DP, 1);
-    chol_inv(h->G, D, h->Linv, Rout, h->R1, h->cholwork, h->st, h->stream);
+    chol_inv(h->G, D, h->Linv, h->R2, nullptr, h->cholwork, h->st, h->stream);
     leg_apply<double>(c, leg, h->Linv, 0, h->Qtmp, 0, Tv, 0, DL, DR, DP, 1, 0, true, false);
+    // R = R2 R1 (both upper triangular, D x D column-major)
+    Gemm<double> g;
+    g.M = g.N = D;
+    g.Kin = D;
+    g.A = h->R2;
+    g.a_plane = (int64_t)D * D;
+    g.sam = 1;
+    g.sak = D;
+    g.B = h->R1;
+    g.b_plane = (int64_t)D * D;
+    g.sbk = 1;
+    g.sbn = D;
+    g.C = Rout;
+    g.c_plane = (int64_t)D * D;
+    g.scm = 1;
+    g.scn = D;
+    c.run(g);
     (void)n;
 }
 
@@ -732,75 +752,132 @@ void absorb(ttn_handle* h, int v, int leg, const double* Op, bool trans) {
     copy_d(h->Ttmp, h->T[v], 2 * n, nullptr, h->stream);
 }
 
+// Up environment of the link above v from its isometry Q: block
+// Q^dag (H_L + H_R + sum_{i in L} n_i A_i) Q and Q^dag n_i Q for every site
+// below, written as the stack E = [H, N_(S_L), N_(S_R)].
+template <typename R>
+void build_up_core(Ctx<R>& c, int DL, int DR, int DP, int sL, int sR, const R* Q, const R* Lb, const R* Rb,
+                   const R* Bb, R* Xs, R* Y, R* E) {
+    const int64_t n = (int64_t)DL * DR * DP, sx = 2 * n;
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
+    leg_apply<R>(c, 0, Lb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
+    leg_apply<R>(c, 0, Lb + 2 * L2, 2 * L2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
+    leg_apply<R>(c, 1, Rb + 2 * R2, 2 * R2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
+    leg_apply<R>(c, 1, Bb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
+    leg_apply_sum<R>(c, 1, Bb + 2 * R2, 2 * R2, Xs + sx, sx, Y, DL, DR, DP, sL, 1);
+    leg_gram<R>(c, 2, Q, Y, 0, E, 0, DL, DR, DP, 1);
+    leg_gram<R>(c, 2, Q, Xs + sx, sx, E + 2 * P2, 2 * P2, DL, DR, DP, sL + sR);
+}
+
+// Down environment of the link above child c (leg `leg` of its parent u,
+// whose tensor Q is canonical toward c): block Hamiltonian of everything
+// outside the subtree of c and W_i = sum_{j outside} V_ij n_j for the sites
+// below c, as the stack E = [H, W_(sites of c)].  Ab: for leg 0 the stack
+// [H_R, A_i] (A_i = sum_{j in R} V_ij n_j), for leg 1 the slots A''_j =
+// sum_{k in L} V_jk n_k at slot 1...
+template <typename R>
+void build_down_core(Ctx<R>& c, int leg, int DL, int DR, int DP, int sL, int sR, const R* Q, const R* Lb,
+                     const R* Rb, const R* Wb, const R* Ab, R* Xs, R* Y, R* E) {
+    const int64_t n = (int64_t)DL * DR * DP, sx = 2 * n;
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
+    const int Dc = leg == 0 ? DL : DR;
+    const int64_t C2 = (int64_t)Dc * Dc;
+    if (leg == 0) {
+        // block: H_R + H_P + sum_{j in R} N_j W_j ; fields W_i (i in L): A_i on R + W_i on P
+        leg_apply<R>(c, 1, Rb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
+        if (Wb) {
+            leg_apply<R>(c, 2, Wb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
+            leg_apply<R>(c, 1, Rb + 2 * R2, 2 * R2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
+            leg_apply_sum<R>(c, 2, Wb + 2 * P2 * (1 + sL), 2 * P2, Xs + sx * (1 + sL), sx, Y, DL, DR, DP, sR, 1);
+        }
+        leg_gram<R>(c, 0, Q, Y, 0, E, 0, DL, DR, DP, 1);
+        leg_apply<R>(c, 1, Ab + 2 * R2, 2 * R2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
+        if (Wb) leg_apply<R>(c, 2, Wb + 2 * P2, 2 * P2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 1);
+        leg_gram<R>(c, 0, Q, Xs + sx, sx, E + 2 * C2, 2 * C2, DL, DR, DP, sL);
+    } else {
+        leg_apply<R>(c, 0, Lb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
+        if (Wb) {
+            leg_apply<R>(c, 2, Wb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
+            leg_apply<R>(c, 0, Lb + 2 * L2, 2 * L2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
+            leg_apply_sum<R>(c, 2, Wb + 2 * P2, 2 * P2, Xs + sx, sx, Y, DL, DR, DP, sL, 1);
+        }
+        leg_gram<R>(c, 1, Q, Y, 0, E, 0, DL, DR, DP, 1);
+        leg_apply<R>(c, 0, Ab + 2 * L2, 2 * L2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
+        if (Wb)
+            leg_apply<R>(c, 2, Wb + 2 * P2 * (1 + sL), 2 * P2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 1);
+        leg_gram<R>(c, 1, Q, Xs + sx * (1 + sL), sx, E + 2 * C2, 2 * C2, DL, DR, DP, sR);
+    }
+}
+
+// In the mixed path the environment contractions run in complex FP32 on
+// FP32 copies of their operands; the FP32 results are made exactly
+// Hermitian while converted back into the FP64 environment store.
 void build_up(ttn_handle* h, int v) {
     Ctx<double> c{h, nullptr};
     const int DL = h->DL[v], DR = h->DR[v], DP = h->DP[v];
     const int sL = sites_left(h, v), sR = sL;
-    const int64_t n = nsize(h, v), sx = 2 * n;
+    const int64_t n = nsize(h, v);
     const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
-    const double* Q = h->T[v];
     const double* Lb = child_block(h, v, 0);
     const double* Rb = child_block(h, v, 1);
     prepare_B(h, c, v, Rb, DR, sL, sR);
-    double* Xs = h->X;
-    double* Y = h->W;
-    leg_apply<double>(c, 0, Lb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
-    leg_apply<double>(c, 0, Lb + 2 * L2, 2 * L2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
-    leg_apply<double>(c, 1, Rb + 2 * R2, 2 * R2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
-    leg_apply<double>(c, 1, h->Bstk, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
-    leg_apply_sum<double>(c, 1, h->Bstk + 2 * R2, 2 * R2, Xs + sx, sx, Y, DL, DR, DP, sL, 1);
-    double* E = h->up[v];
-    leg_gram(c, 2, Q, Y, 0, E, 0, DL, DR, DP, 1);
-    leg_gram(c, 2, Q, Xs + sx, sx, E + 2 * P2, 2 * P2, DL, DR, DP, sL + sR);
+    if (h->prec == TTN_PREC_FP32) {
+        Ctx<float> cf{h, nullptr};
+        float* Qf = h->Xf;   // slot 0 of the FP32 stack is free during an environment build
+        chk(h, h->Ef, (1 + sL + sR) * P2, "fp32 environment staging");
+        convert_d2f(h->T[v], Qf, 2 * n, nullptr, h->stream);
+        convert_d2f(Lb, h->Lf, 2 * (1 + sL) * L2, nullptr, h->stream);
+        convert_d2f(Rb, h->Rf, 2 * (1 + sR) * R2, nullptr, h->stream);
+        convert_d2f(h->Bstk, h->Bf, 2 * (1 + sL) * R2, nullptr, h->stream);
+        build_up_core<float>(cf, DL, DR, DP, sL, sR, Qf, h->Lf, h->Rf, h->Bf, h->Xf, h->Yf, h->Ef);
+        herm_f2d(h->Ef, h->up[v], DP, 1 + sL + sR, h->stream);
+    } else {
+        build_up_core<double>(c, DL, DR, DP, sL, sR, h->T[v], Lb, Rb, h->Bstk, h->X, h->W, h->up[v]);
+    }
 }
 
-// down environment of the link above c, from its parent u canonical toward c
 void build_down(ttn_handle* h, int cnode) {
     Ctx<double> c{h, nullptr};
     const int u = h->parent[cnode];
     const int leg = leg_in_parent(h, cnode);
     const int DL = h->DL[u], DR = h->DR[u], DP = h->DP[u];
     const int sL = sites_left(h, u), sR = sL;
-    const int64_t n = nsize(h, u), sx = 2 * n;
+    const int64_t n = nsize(h, u);
     const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
-    const double* Q = h->T[u];
     const double* Lb = child_block(h, u, 0);
     const double* Rb = child_block(h, u, 1);
     const double* Wb = u == h->root ? nullptr : h->dn[u];
-    double* Xs = h->X;
-    double* Y = h->W;
-    double* E = h->dn[cnode];
     const int Dc = leg == 0 ? DL : DR;
     const int64_t C2 = (int64_t)Dc * Dc;
+    const double* Ab;
+    int64_t Alen;
     if (leg == 0) {
-        // block: H_R + H_P + sum_{j in R} N_j W_j ; fields W_i (i in L): A_i on R + W_i on P
-        leg_apply<double>(c, 1, Rb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
-        if (Wb) {
-            leg_apply<double>(c, 2, Wb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
-            leg_apply<double>(c, 1, Rb + 2 * R2, 2 * R2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
-            leg_apply_sum<double>(c, 2, Wb + 2 * P2 * (1 + sL), 2 * P2, Xs + sx * (1 + sL), sx, Y, DL, DR,
-                                  DP, sR, 1);
-        }
-        leg_gram(c, 0, Q, Y, 0, E, 0, DL, DR, DP, 1);
-        prepare_B(h, c, u, Rb, DR, sL, sR);   // A_i = sum_{j in R} V_ij N_j
-        leg_apply<double>(c, 1, h->Bstk + 2 * R2, 2 * R2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
-        if (Wb) leg_apply<double>(c, 2, Wb + 2 * P2, 2 * P2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 1);
-        leg_gram(c, 0, Q, Xs + sx, sx, E + 2 * C2, 2 * C2, DL, DR, DP, sL);
+        prepare_B(h, c, u, Rb, DR, sL, sR);   // [H_R, A_i = sum_{j in R} V_ij N_j]
+        Ab = h->Bstk;
+        Alen = (1 + sL) * R2;
     } else {
-        leg_apply<double>(c, 0, Lb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 0);
-        if (Wb) {
-            leg_apply<double>(c, 2, Wb, 0, Q, 0, Y, 0, DL, DR, DP, 1, 1);
-            leg_apply<double>(c, 0, Lb + 2 * L2, 2 * L2, Q, 0, Xs + sx, sx, DL, DR, DP, sL, 0);
-            leg_apply_sum<double>(c, 2, Wb + 2 * P2, 2 * P2, Xs + sx, sx, Y, DL, DR, DP, sL, 1);
-        }
-        leg_gram(c, 1, Q, Y, 0, E, 0, DL, DR, DP, 1);
-        // A''_j = sum_{k in L} V_jk N_k (left operators), j in R
+        // A''_j = sum_{k in L} V_jk N_k (left operators), j in R, at slots 1..
         vsum_stack(c, Lb, DL, sL, h->vLR[u], sR, h->Astk + 2 * L2);
-        leg_apply<double>(c, 0, h->Astk + 2 * L2, 2 * L2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR, DP, sR, 0);
-        if (Wb)
-            leg_apply<double>(c, 2, Wb + 2 * P2 * (1 + sL), 2 * P2, Q, 0, Xs + sx * (1 + sL), sx, DL, DR,
-                              DP, sR, 1);
-        leg_gram(c, 1, Q, Xs + sx * (1 + sL), sx, E + 2 * C2, 2 * C2, DL, DR, DP, sR);
+        Ab = h->Astk;
+        Alen = (1 + sR) * L2;
+    }
+    if (h->prec == TTN_PREC_FP32) {
+        Ctx<float> cf{h, nullptr};
+        float* Qf = h->Xf;
+        chk(h, h->Ef, (1 + (leg == 0 ? sL : sR)) * C2, "fp32 environment staging");
+        convert_d2f(h->T[u], Qf, 2 * n, nullptr, h->stream);
+        convert_d2f(Lb, h->Lf, 2 * (1 + sL) * L2, nullptr, h->stream);
+        convert_d2f(Rb, h->Rf, 2 * (1 + sR) * R2, nullptr, h->stream);
+        if (Wb) convert_d2f(Wb, h->Wf, 2 * (1 + sL + sR) * P2, nullptr, h->stream);
+        if (leg == 0)
+            convert_d2f(Ab, h->Bf, 2 * Alen, nullptr, h->stream);
+        else
+            convert_d2f(Ab + 2 * L2, h->Bf + 2 * L2, 2 * (Alen - L2), nullptr, h->stream);
+        build_down_core<float>(cf, leg, DL, DR, DP, sL, sR, Qf, h->Lf, h->Rf, Wb ? h->Wf : nullptr, h->Bf, h->Xf,
+                               h->Yf, h->Ef);
+        herm_f2d(h->Ef, h->dn[cnode], Dc, 1 + (leg == 0 ? sL : sR), h->stream);
+    } else {
+        build_down_core<double>(c, leg, DL, DR, DP, sL, sR, h->T[u], Lb, Rb, Wb, Ab, h->X, h->W, h->dn[cnode]);
     }
 }
 

@@ -461,8 +461,8 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
         int splits = 1;
         const int ktiles = K / 16;
-        if (tiles < 512 && ktiles >= 4) {
-            splits = (int)std::min<int64_t>((1024 + tiles - 1) / tiles, ktiles / 2);
+        if (tiles < 256 && ktiles >= 8) {
+            splits = (int)std::min<int64_t>((512 + tiles - 1) / tiles, ktiles / 4);
             const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
             const int64_t cap = per > 0 ? ws.bytes / per : 1;
             if (splits > cap) splits = (int)cap;
@@ -515,8 +515,8 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
     const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
     const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
     int splits = 1;
-    if (K > 0 && tiles < 512 && K > 4 * BK) {
-        splits = (int)std::min<int64_t>((1024 + tiles - 1) / tiles, K / (2 * BK));
+    if (K > 0 && tiles < 256 && K > 8 * BK) {
+        splits = (int)std::min<int64_t>((512 + tiles - 1) / tiles, K / (4 * BK));
         const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
         const int64_t cap = per > 0 ? ws.bytes / per : 1;
         if (splits > cap) splits = (int)cap;
@@ -582,19 +582,22 @@ __global__ void k_norm2_partial(const double* x, int64_t n, double* partial, con
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
+__device__ inline double wave_sum_partials(const double* partial, int nb) {
+    double s = 0;
+    for (int i = threadIdx.x; i < nb; i += 64) s += partial[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    return s;   // valid in lane 0
+}
+
 __global__ void k_sum_partial(const double* partial, int nb, double* out, const int* skip) {
     if (skip && *skip) return;
-    if (threadIdx.x == 0) {
-        double s = 0;
-        for (int i = 0; i < nb; ++i) s += partial[i];
-        *out = s;
-    }
+    const double s = wave_sum_partials(partial, nb);
+    if (threadIdx.x == 0) *out = s;
 }
 
 __global__ void k_lz_begin(const double* partial, int nb, LanczosDev* lz) {
+    const double s = wave_sum_partials(partial, nb);
     if (threadIdx.x == 0) {
-        double s = 0;
-        for (int i = 0; i < nb; ++i) s += partial[i];
         lz->beta0 = sqrt(s);
         lz->zero = (s == 0.0) ? 1 : 0;
         lz->done = lz->zero;
@@ -620,14 +623,20 @@ __global__ void k_multidot_partial(const double* V, int kcount, const double* w,
     for (int k = 0; k < KRYLOV_MAX; ++k) re[k] = im[k] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        double vr[KRYLOV_MAX], vi[KRYLOV_MAX];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k) {
+            if (k < kcount) {
+                vr[k] = V[2 * n * k + i];
+                vi[k] = V[2 * n * k + n + i];
+            }
+        }
         const double wr = w[i], wi = w[i + n];
 #pragma unroll
         for (int k = 0; k < KRYLOV_MAX; ++k) {
             if (k < kcount) {
-                const double* v = V + 2 * n * k;
-                const double vr = v[i], vi = v[i + n];
-                re[k] += vr * wr + vi * wi;
-                im[k] += vr * wi - vi * wr;
+                re[k] += vr[k] * wr + vi[k] * wi;
+                im[k] += vr[k] * wi - vi[k] * wr;
             }
         }
     }
@@ -664,32 +673,71 @@ __global__ void k_multidot_final(const double* partial, int nb, int kcount, Lanc
     }
 }
 
-__global__ void k_multi_subtract(const double* V, int kcount, double* w, int64_t n,
-                                 const LanczosDev* lz) {
+// w -= sum_k c_k V_k; then, per block, partial sums of either the new
+// projections conj(V_k) w (mode 1) or |w|^2 (mode 2); mode 0 only subtracts.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_sub_fused(const double* V, int kcount, double* w, int64_t n,
+                                                   double* partial, const LanczosDev* lz) {
     if (lz->done) return;
     __shared__ double c[2 * KRYLOV_MAX];
+    __shared__ double sh[16];
     if (threadIdx.x < 2 * KRYLOV_MAX) c[threadIdx.x] = lz->c[threadIdx.x];
     __syncthreads();
+    double pr[KRYLOV_MAX], pi[KRYLOV_MAX], nrm = 0;
+#pragma unroll
+    for (int k = 0; k < KRYLOV_MAX; ++k) pr[k] = pi[k] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        double vr[KRYLOV_MAX], vi[KRYLOV_MAX];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k) {
+            if (k < kcount) {
+                vr[k] = V[2 * n * k + i];
+                vi[k] = V[2 * n * k + n + i];
+            }
+        }
         double wr = w[i], wi = w[i + n];
-        for (int k = 0; k < kcount; ++k) {
-            const double* v = V + 2 * n * k;
-            const double vr = v[i], vi = v[i + n];
-            const double cr = c[2 * k], ci = c[2 * k + 1];
-            wr -= cr * vr - ci * vi;
-            wi -= cr * vi + ci * vr;
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k) {
+            if (k < kcount) {
+                const double cr = c[2 * k], ci = c[2 * k + 1];
+                wr -= cr * vr[k] - ci * vi[k];
+                wi -= cr * vi[k] + ci * vr[k];
+            }
         }
         w[i] = wr;
         w[i + n] = wi;
+        if (MODE == 1) {
+#pragma unroll
+            for (int k = 0; k < KRYLOV_MAX; ++k) {
+                if (k < kcount) {
+                    pr[k] += vr[k] * wr + vi[k] * wi;
+                    pi[k] += vr[k] * wi - vi[k] * wr;
+                }
+            }
+        } else if (MODE == 2) {
+            nrm += wr * wr + wi * wi;
+        }
+    }
+    if (MODE == 1) {
+        for (int k = 0; k < kcount; ++k) {
+            const double a = block_sum(pr[k], sh);
+            if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2] = a;
+            const double b2 = block_sum(pi[k], sh);
+            if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2 + 1] = b2;
+        }
+    } else if (MODE == 2) {
+        const double a = block_sum(nrm, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = a;
     }
 }
 
 __global__ void k_lz_beta(const double* partial, int nb, LanczosDev* lz, int j, double tol) {
     if (lz->done) return;
+    double s = 0;
+    for (int i = threadIdx.x; i < nb; i += 64) s += partial[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (threadIdx.x == 0) {
-        double s = 0;
-        for (int i = 0; i < nb; ++i) s += partial[i];
         const double b = sqrt(s);
         const double bprev = j > 0 ? lz->beta[j - 1] : 0.0;
         if (!(b > tol * (fabs(lz->alpha[j]) + bprev)))
@@ -834,7 +882,22 @@ void lz_project(const double* V, int kcount, const double* w, int64_t n, double*
 
 void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s) {
     if (g_dry_run) return;
-    hipLaunchKernelGGL(k_multi_subtract, dim3(grid_for(n)), dim3(256), 0, s, V, kcount, w, n, lz);
+    hipLaunchKernelGGL(k_sub_fused<0>, dim3(grid_for(n)), dim3(256), 0, s, V, kcount, w, n, (double*)nullptr, lz);
+}
+
+void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, double* partial, int nb,
+                         LanczosDev* lz, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_sub_fused<1>, dim3(nb), dim3(256), 0, s, V, kcount, w, n, partial, lz);
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64 * kcount), 0, s, partial, nb, kcount, lz, -1);
+}
+
+void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
+                      double* partial, int nb, double tol, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_sub_fused<2>, dim3(nb), dim3(256), 0, s, V, kcount, w, n, partial, lz);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s, partial, nb, lz, j, tol);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j);
 }
 
 void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
@@ -892,7 +955,25 @@ __global__ void k_transpose(const double* x, double* y, int rows, int cols) {
         y[n + c + (int64_t)cols * r] = x[n + e];
     }
 }
+__global__ void k_herm_f2d(const float* in, double* out, int D, int count) {
+    const int64_t D2 = (int64_t)D * D, total = D2 * count;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / D2, ab = e % D2;
+        const int a = (int)(ab % D), b = (int)(ab / D);
+        const float* m = in + 2 * D2 * k;
+        const int64_t t = b + (int64_t)D * a;
+        out[2 * D2 * k + ab] = 0.5 * ((double)m[ab] + (double)m[t]);
+        out[2 * D2 * k + D2 + ab] = 0.5 * ((double)m[D2 + ab] - (double)m[D2 + t]);
+    }
+}
 }  // namespace
+
+void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s) {
+    if (g_dry_run) return;
+    const int64_t total = (int64_t)D * D * count;
+    hipLaunchKernelGGL(k_herm_f2d, dim3(grid_for(total)), dim3(256), 0, s, in, out, D, count);
+}
 
 void convert_d2f(const double* x, float* y, int64_t count, const int* skip, hipStream_t s) {
     if (g_dry_run) return;
@@ -922,79 +1003,138 @@ void transpose_c(const double* x, double* y, int rows, int cols, hipStream_t s) 
 namespace {
 
 constexpr int CHOL_THREADS = 512;
+constexpr int CHOL_PANEL = 16;
 constexpr int CHOL_LDS_MAX = 128;   // packed lower triangle of 128 x 128 fits LDS
 
 __device__ inline int64_t pidx(int i, int j, int D) {   // packed lower, column-major, i >= j
     return (int64_t)j * D - (int64_t)j * (j - 1) / 2 + (i - j);
 }
 
-template <bool LDS>
+// Panel-blocked Cholesky G = L L^H and in-place inverse X = L^{-1} (lower,
+// packed, column-major).  Each panel of P columns (Cholesky) or P rows
+// (inverse) is processed by the first wave with the panel held in registers
+// (RPL rows or columns per lane) and pivots / column entries broadcast by
+// cross-lane shuffles; the rank-P updates of the rest of the matrix use the
+// whole workgroup between barriers.
+template <bool LDS, int RPL, int P>
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int D, double* Linv,
                                                            double* R, const double* Rprev,
                                                            double* work, StepDev* st) {
     __shared__ double sLre[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) / 2 : 1];
     __shared__ double sLim[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) / 2 : 1];
-    __shared__ double col_re[LDS ? CHOL_LDS_MAX : 1], col_im[LDS ? CHOL_LDS_MAX : 1];
     __shared__ int s_bad;
     const int64_t np = (int64_t)D * (D + 1) / 2;
     double* Lre = LDS ? sLre : work;
     double* Lim = LDS ? sLim : work + np;
-    double* cr = LDS ? col_re : work + 2 * np;
-    double* ci = LDS ? col_im : work + 2 * np + D;
-    const int tid = threadIdx.x;
-    const int tx = tid % 32, ty = tid / 32;      // 32 x 16 thread grid
-    constexpr int TY = CHOL_THREADS / 32;
+    double* Tre = work + 2 * np;                 // rows x P copy of L for the inverse
+    double* Tim = Tre + (int64_t)D * P;
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const int64_t DD = (int64_t)D * D;
     if (tid == 0) s_bad = 0;
-    for (int j = ty; j < D; j += TY)
-        for (int i = j + tx; i < D; i += 32) {
-            Lre[pidx(i, j, D)] = G[i + (int64_t)D * j];
-            Lim[pidx(i, j, D)] = G[DD + i + (int64_t)D * j];
+    for (int64_t e = tid; e < DD; e += CHOL_THREADS) {
+        const int i = (int)(e % D), j = (int)(e / D);
+        if (i >= j) {
+            Lre[pidx(i, j, D)] = G[e];
+            Lim[pidx(i, j, D)] = G[DD + e];
         }
+    }
     __syncthreads();
-    // right-looking Cholesky G = L L^H (lower, packed)
-    for (int j = 0; j < D; ++j) {
-        const int64_t jj = pidx(j, j, D);
-        if (tid == 0) {
-            const double piv = Lre[jj];
-            if (!(piv > 1e-290)) s_bad = 1;
-            Lre[jj] = sqrt(piv > 1e-290 ? piv : 1e-290);
-            Lim[jj] = 0.0;
-        }
-        __syncthreads();
-        const double dinv = 1.0 / Lre[jj];
-        for (int i = j + 1 + tid; i < D; i += CHOL_THREADS) {
-            const int64_t q = pidx(i, j, D);
-            Lre[q] *= dinv;
-            Lim[q] *= dinv;
-            cr[i] = Lre[q];
-            ci[i] = Lim[q];
-        }
-        __syncthreads();
-        // L[i][k] -= L[i][j] conj(L[k][j]) for j < k <= i
-        for (int k = j + 1 + ty; k < D; k += TY) {
-            const double br = cr[k], bi = ci[k];
-            const int64_t base = pidx(k, k, D) - k;
-            for (int i = k + tx; i < D; i += 32) {
-                const double ar = cr[i], ai = ci[i];
-                Lre[base + i] -= ar * br + ai * bi;
-                Lim[base + i] -= ai * br - ar * bi;
+    // ---------------- Cholesky ----------------
+    for (int p0 = 0; p0 < D; p0 += P) {
+        const int pe = min(p0 + P, D);
+        if (wave == 0) {
+            double xr[RPL][P], xi[RPL][P];   // rows p0 + lane + 64 r, columns p0 + c
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = p0 + lane + 64 * r;
+#pragma unroll
+                for (int c = 0; c < P; ++c) {
+                    const bool ok = i < D && p0 + c < pe && p0 + c <= i;
+                    const int64_t q = ok ? pidx(i, p0 + c, D) : 0;
+                    xr[r][c] = ok ? Lre[q] : 0.0;
+                    xi[r][c] = ok ? Lim[q] : 0.0;
+                }
             }
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                if (p0 + j < pe) {
+                    const double piv = __shfl(xr[0][j], j, 64);   // diagonal: row p0 + j is lane j
+                    bad = bad || !(piv > 1e-290);
+                    const double d = sqrt(piv > 1e-290 ? piv : 1e-290), dinv = 1.0 / d;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) {
+                        const int i = p0 + lane + 64 * r;
+                        if (i == p0 + j) {
+                            xr[r][j] = d;
+                            xi[r][j] = 0.0;
+                        } else if (i > p0 + j) {
+                            xr[r][j] *= dinv;
+                            xi[r][j] *= dinv;
+                        }
+                    }
+#pragma unroll
+                    for (int k = j + 1; k < P; ++k) {
+                        if (p0 + k < pe) {
+                            const double lr = __shfl(xr[0][j], k, 64), li = __shfl(xi[0][j], k, 64);
+#pragma unroll
+                            for (int r = 0; r < RPL; ++r) {
+                                const int i = p0 + lane + 64 * r;
+                                if (i >= p0 + k) {   // L[i][k] -= L[i][j] conj(L[k][j])
+                                    xr[r][k] -= xr[r][j] * lr + xi[r][j] * li;
+                                    xi[r][k] -= xi[r][j] * lr - xr[r][j] * li;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            if (bad && lane == 0) s_bad = 1;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = p0 + lane + 64 * r;
+#pragma unroll
+                for (int c = 0; c < P; ++c)
+                    if (i < D && p0 + c < pe && p0 + c <= i) {
+                        const int64_t q = pidx(i, p0 + c, D);
+                        Lre[q] = xr[r][c];
+                        Lim[q] = xi[r][c];
+                    }
+            }
+        }
+        __syncthreads();
+        // trailing update: L[i][k] -= sum_{j in panel} L[i][j] conj(L[k][j]), pe <= k <= i
+        const int rn = D - pe;
+        for (int64_t e = tid; e < (int64_t)rn * rn; e += CHOL_THREADS) {
+            const int ii = (int)(e % rn), kk = (int)(e / rn);
+            if (ii < kk) continue;
+            const int i = pe + ii, k = pe + kk;
+            double sr = 0, si = 0;
+            for (int j = p0; j < pe; ++j) {
+                const int64_t cj = pidx(j, j, D) - j;
+                const double ar = Lre[cj + i], ai = Lim[cj + i];
+                const double br = Lre[cj + k], bi = Lim[cj + k];
+                sr += ar * br + ai * bi;
+                si += ai * br - ar * bi;
+            }
+            const int64_t q = pidx(i, k, D);
+            Lre[q] -= sr;
+            Lim[q] -= si;
         }
         __syncthreads();
     }
     // R = L^H, or L^H Rprev:  R[k][a] = sum_{j=k}^{a} conj(L[j][k]) Rprev[j][a]
-    for (int e = tid; e < DD; e += CHOL_THREADS) {
+    for (int64_t e = tid; e < DD; e += CHOL_THREADS) {
         const int k = (int)(e % D), a = (int)(e / D);
         double rr = 0, ri = 0;
         if (a >= k) {
+            const int64_t ck = pidx(k, k, D) - k;
             if (!Rprev) {
-                rr = Lre[pidx(a, k, D)];
-                ri = -Lim[pidx(a, k, D)];
+                rr = Lre[ck + a];
+                ri = -Lim[ck + a];
             } else {
-                const int64_t base = pidx(k, k, D) - k;
                 for (int j = k; j <= a; ++j) {
-                    const double lr = Lre[base + j], li = -Lim[base + j];
+                    const double lr = Lre[ck + j], li = -Lim[ck + j];
                     const double pr = Rprev[j + (int64_t)D * a], pi = Rprev[DD + j + (int64_t)D * a];
                     rr += lr * pr - li * pi;
                     ri += lr * pi + li * pr;
@@ -1014,43 +1154,117 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int 
         if (s_bad || !(mn == mn)) atomicExch(&st->bad, 1);
         if (mn > 0) atomicMin(&st->min_rdiag_bits, (unsigned long long)__double_as_longlong(mn));
     }
-    // in-place inverse X = L^{-1} by elimination on the identity:
-    // step k: row k of X scaled by 1/L[k][k]; then rows i > k lose L[i][k] X[k][:]
-    for (int k = 0; k < D; ++k) {
-        const int64_t kk = pidx(k, k, D);
-        const double d = 1.0 / Lre[kk];   // (k, k) is not written by step k-1
-        __syncthreads();
-        for (int j = tid; j < k; j += CHOL_THREADS) {
-            const int64_t q = pidx(k, j, D);
-            Lre[q] *= d;
-            Lim[q] *= d;
-        }
-        for (int i = k + 1 + tid; i < D; i += CHOL_THREADS) {
-            const int64_t q = pidx(i, k, D);
-            cr[i] = Lre[q];
-            ci[i] = Lim[q];
-        }
-        if (tid == 0) {
-            Lre[kk] = d;
-            Lim[kk] = 0.0;
-        }
-        __syncthreads();
-        // X[i][j] = (j == k ? 0 : X[i][j]) - L[i][k] X[k][j]   for i > k, j <= k
-        for (int j = ty; j <= k; j += TY) {
-            const int64_t qk = pidx(k, j, D);
-            const double xr = Lre[qk], xi = Lim[qk];
-            const int64_t base = pidx(j, j, D) - j;
-            for (int i = k + 1 + tx; i < D; i += 32) {
-                const double lr = cr[i], li = ci[i];
-                const double or_ = (j == k) ? 0.0 : Lre[base + i];
-                const double oi = (j == k) ? 0.0 : Lim[base + i];
-                Lre[base + i] = or_ - (lr * xr - li * xi);
-                Lim[base + i] = oi - (lr * xi + li * xr);
+    // ---------------- inverse by elimination on the identity ----------------
+    // Position (i, j), i > j, holds L[i][j] until step j and the partial
+    // X[i][j] afterwards; the diagonal becomes 1 / L[i][i].
+    for (int p0 = 0; p0 < D; p0 += P) {
+        const int pe = min(p0 + P, D);
+        if (wave == 0) {
+            double yr[P][RPL], yi[P][RPL];   // panel rows p0 + t, columns lane + 64 s
+#pragma unroll
+            for (int t = 0; t < P; ++t)
+#pragma unroll
+                for (int sl = 0; sl < RPL; ++sl) {
+                    const int c = lane + 64 * sl, k = p0 + t;
+                    const bool ok = k < pe && c <= k;
+                    const int64_t q = ok ? pidx(k, c, D) : 0;
+                    yr[t][sl] = ok ? Lre[q] : 0.0;
+                    yi[t][sl] = ok ? Lim[q] : 0.0;
+                }
+#pragma unroll
+            for (int t = 0; t < P; ++t) {
+                const int k = p0 + t;
+                if (k < pe) {
+                    const int kl = k & 63, ks = k >> 6;
+                    double sel = 0.0;
+#pragma unroll
+                    for (int sl = 0; sl < RPL; ++sl)
+                        if (sl == ks) sel = yr[t][sl];
+                    const double d = 1.0 / __shfl(sel, kl, 64);
+                    // column k of the later panel rows (still L values)
+                    double cr[P], ci[P];
+#pragma unroll
+                    for (int u = t + 1; u < P; ++u) {
+                        double a = 0.0, b2 = 0.0;
+#pragma unroll
+                        for (int sl = 0; sl < RPL; ++sl)
+                            if (sl == ks) {
+                                a = yr[u][sl];
+                                b2 = yi[u][sl];
+                            }
+                        cr[u] = __shfl(a, kl, 64);
+                        ci[u] = __shfl(b2, kl, 64);
+                    }
+#pragma unroll
+                    for (int sl = 0; sl < RPL; ++sl) {
+                        const int c = lane + 64 * sl;
+                        if (c < k) {
+                            yr[t][sl] *= d;
+                            yi[t][sl] *= d;
+                        } else if (c == k) {
+                            yr[t][sl] = d;
+                            yi[t][sl] = 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int u = t + 1; u < P; ++u) {
+                        if (p0 + u < pe) {
+#pragma unroll
+                            for (int sl = 0; sl < RPL; ++sl) {
+                                const int c = lane + 64 * sl;
+                                if (c <= k) {
+                                    const double orr = (c == k) ? 0.0 : yr[u][sl];
+                                    const double oii = (c == k) ? 0.0 : yi[u][sl];
+                                    yr[u][sl] = orr - (cr[u] * yr[t][sl] - ci[u] * yi[t][sl]);
+                                    yi[u][sl] = oii - (cr[u] * yi[t][sl] + ci[u] * yr[t][sl]);
+                                }
+                            }
+                        }
+                    }
+                }
             }
+#pragma unroll
+            for (int t = 0; t < P; ++t)
+#pragma unroll
+                for (int sl = 0; sl < RPL; ++sl) {
+                    const int c = lane + 64 * sl, k = p0 + t;
+                    if (k < pe && c <= k) {
+                        const int64_t q = pidx(k, c, D);
+                        Lre[q] = yr[t][sl];
+                        Lim[q] = yi[t][sl];
+                    }
+                }
         }
+        const int rn = D - pe;
+        // copy L[i][panel] for the rows below the panel (not touched by wave 0)
+        for (int e = tid; e < rn * (pe - p0); e += CHOL_THREADS) {
+            const int r = e % rn, c = e / rn;
+            const int64_t q = pidx(pe + r, p0 + c, D);
+            Tre[r + (int64_t)D * c] = Lre[q];
+            Tim[r + (int64_t)D * c] = Lim[q];
+        }
+        __syncthreads();
+        // rows i >= pe: X[i][j] = (j in panel ? 0 : X[i][j]) - sum_{k in panel, k >= j} L[i][k] X[k][j]
+        for (int64_t e = tid; e < (int64_t)rn * pe; e += CHOL_THREADS) {
+            const int r = (int)(e % rn), j = (int)(e / rn);
+            const int i = pe + r;
+            double sr = 0, si = 0;
+            for (int k = max(j, p0); k < pe; ++k) {
+                const double lr = Tre[r + (int64_t)D * (k - p0)], li = Tim[r + (int64_t)D * (k - p0)];
+                const int64_t qk = pidx(k, j, D);
+                const double xr = Lre[qk], xi = Lim[qk];
+                sr += lr * xr - li * xi;
+                si += lr * xi + li * xr;
+            }
+            const int64_t qi = pidx(i, j, D);
+            const double or_ = (j >= p0) ? 0.0 : Lre[qi];
+            const double oi = (j >= p0) ? 0.0 : Lim[qi];
+            Lre[qi] = or_ - sr;
+            Lim[qi] = oi - si;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < DD; e += CHOL_THREADS) {
+    for (int64_t e = tid; e < DD; e += CHOL_THREADS) {
         const int i = (int)(e % D), j = (int)(e / D);
         double xr = 0, xi = 0;
         if (i >= j) {
@@ -1068,11 +1282,11 @@ void chol_inv(const double* G, int D, double* Linv, double* R, const double* Rpr
               StepDev* st, hipStream_t s) {
     if (g_dry_run) return;
     if (D <= CHOL_LDS_MAX)
-        hipLaunchKernelGGL(k_chol_inv<true>, dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R, Rprev,
+        hipLaunchKernelGGL((k_chol_inv<true, 2, 16>), dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R, Rprev,
                            work, st);
     else
-        hipLaunchKernelGGL(k_chol_inv<false>, dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R,
-                           Rprev, work, st);
+        hipLaunchKernelGGL((k_chol_inv<false, 4, 8>), dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R, Rprev,
+                           work, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -88,6 +88,12 @@ void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* pa
 void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
                 LanczosDev* lz, int alpha_index, hipStream_t s);
 void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s);
+// w -= V c, then c <- V^H w (second Gram-Schmidt pass), fused
+void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, double* partial, int nb,
+                         LanczosDev* lz, hipStream_t s);
+// w -= V c, then beta_j = ||w||, breakdown test, v_{j+1} = w / beta_j
+void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
+                      double* partial, int nb, double tol, hipStream_t s);
 void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
              double tol, hipStream_t s);
 void lz_expm(LanczosDev* lz, double tau, StepDev* st, hipStream_t s);
@@ -99,6 +105,8 @@ void convert_f2d(const float* x, double* y, int64_t count, const int* skip, hipS
 void copy_d(const double* x, double* y, int64_t count, const int* skip, hipStream_t s);
 void transpose_c(const double* x, double* y, int rows, int cols, hipStream_t s);
 void fill_zero_d(double* y, int64_t count, hipStream_t s);
+// out_k = (in_k + in_k^H) / 2 for `count` planar D x D FP32 matrices, into FP64
+void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s);
 
 // Cholesky of a Hermitian D x D Gram matrix G (planar, column-major):
 // G = L L^H.  Writes Linv (lower, L^{-1}) and R = L^H (upper), or R = L^H * Rprev
