@@ -1,0 +1,548 @@
+// Complex contraction (GEMM) kernels of the TDVP library for gfx950: a tiled
+// VALU fallback, the MFMA kernel and the split-K reduction, with the host-side
+// dispatch cgemm().
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+
+#include "ttn_internal.h"
+
+namespace ttn {
+
+namespace {
+
+constexpr int GEMM_THREADS = 256;
+
+template <typename R, int BM, int BN, int BK>
+__global__ __launch_bounds__(GEMM_THREADS) void k_cgemm(Gemm<R> g, int tilesM, int tilesN,
+                                                        int splits, int kchunk, R* partial,
+                                                        int a_mfast, int b_nfast) {
+    if (g.skip && *g.skip) return;
+    constexpr int TM = BM / 16, TN = BN / 16;
+    __shared__ R As[2][BK][BM + 1];
+    __shared__ R Bs[2][BK][BN + 1];
+    int64_t bid = blockIdx.x;
+    const int tm = bid % tilesM;
+    bid /= tilesM;
+    const int tn = bid % tilesN;
+    bid /= tilesN;
+    const int sp = bid % splits;
+    bid /= splits;
+    const int b = (int)bid;
+    const int b1 = b % g.B1, b2 = b / g.B1;
+    const R* A = g.A + b1 * g.sab1 + b2 * g.sab2;
+    const R* B = g.B + b1 * g.sbb1 + b2 * g.sbb2;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int K = g.Kin * g.Kout;
+    const int kb = sp * kchunk;
+    const int ke = min(K, kb + kchunk);
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
+    R acc_re[TM][TN], acc_im[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            acc_re[i][j] = 0;
+            acc_im[i][j] = 0;
+        }
+    const R sa = g.conjA ? R(-1) : R(1);
+    const R sb = g.conjB ? R(-1) : R(1);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        for (int e = tid; e < BM * BK; e += GEMM_THREADS) {
+            int mm, kk;
+            if (a_mfast) {
+                mm = e % BM;
+                kk = e / BM;
+            } else {
+                kk = e % BK;
+                mm = e / BK;
+            }
+            const int m = m0 + mm, k = k0 + kk;
+            R re = 0, im = 0;
+            if (m < g.M && k < ke) {
+                const int kin = k % g.Kin, kout = k / g.Kin;
+                const int64_t off = (int64_t)m * g.sam + (int64_t)kin * g.sak + (int64_t)kout * g.sako;
+                re = A[off];
+                im = sa * A[off + g.a_plane];
+            }
+            As[0][kk][mm] = re;
+            As[1][kk][mm] = im;
+        }
+        for (int e = tid; e < BN * BK; e += GEMM_THREADS) {
+            int nn, kk;
+            if (b_nfast) {
+                nn = e % BN;
+                kk = e / BN;
+            } else {
+                kk = e % BK;
+                nn = e / BK;
+            }
+            const int n = n0 + nn, k = k0 + kk;
+            R re = 0, im = 0;
+            if (n < g.N && k < ke) {
+                const int kin = k % g.Kin, kout = k / g.Kin;
+                const int64_t off = (int64_t)n * g.sbn + (int64_t)kin * g.sbk + (int64_t)kout * g.sbko;
+                re = B[off];
+                im = sb * B[off + g.b_plane];
+            }
+            Bs[0][kk][nn] = re;
+            Bs[1][kk][nn] = im;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < BK; ++kk) {
+            R ar[TM], ai[TM], br[TN], bi[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                ar[i] = As[0][kk][tx + 16 * i];
+                ai[i] = As[1][kk][tx + 16 * i];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                br[j] = Bs[0][kk][ty + 16 * j];
+                bi[j] = Bs[1][kk][ty + 16 * j];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    acc_re[i][j] = fma(ar[i], br[j], acc_re[i][j]);
+                    acc_re[i][j] = fma(-ai[i], bi[j], acc_re[i][j]);
+                    acc_im[i][j] = fma(ar[i], bi[j], acc_im[i][j]);
+                    acc_im[i][j] = fma(ai[i], br[j], acc_im[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+    if (splits == 1) {
+        R* C = g.C + b1 * g.scb1 + b2 * g.scb2;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int m = m0 + tx + 16 * i;
+            if (m >= g.M) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + ty + 16 * j;
+                if (n >= g.N) continue;
+                const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
+                R re = g.alpha * acc_re[i][j], im = g.alpha * acc_im[i][j];
+                if (g.beta) {
+                    re += C[off];
+                    im += C[off + g.c_plane];
+                }
+                C[off] = re;
+                C[off + g.c_plane] = im;
+            }
+        }
+    } else {
+        const int64_t MN = (int64_t)g.M * g.N;
+        const int nbatch = g.B1 * g.B2;
+        R* P = partial + ((int64_t)sp * nbatch + b) * 2 * MN;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int m = m0 + tx + 16 * i;
+            if (m >= g.M) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + ty + 16 * j;
+                if (n >= g.N) continue;
+                P[m + (int64_t)g.M * n] = acc_re[i][j];
+                P[MN + m + (int64_t)g.M * n] = acc_im[i][j];
+            }
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_splitk_reduce(Gemm<R> g, int splits, const R* partial) {
+    if (g.skip && *g.skip) return;
+    const int64_t MN = (int64_t)g.M * g.N;
+    const int nbatch = g.B1 * g.B2;
+    const int64_t total = MN * nbatch;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / MN);
+        const int64_t mn = e % MN;
+        const int m = (int)(mn % g.M), n = (int)(mn / g.M);
+        R re = 0, im = 0;
+        for (int s = 0; s < splits; ++s) {
+            const R* P = partial + ((int64_t)s * nbatch + b) * 2 * MN;
+            re += P[mn];
+            im += P[MN + mn];
+        }
+        const int b1 = b % g.B1, b2 = b / g.B1;
+        R* C = g.C + b1 * g.scb1 + b2 * g.scb2;
+        const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
+        re *= g.alpha;
+        im *= g.alpha;
+        if (g.beta) {
+            re += C[off];
+            im += C[off + g.c_plane];
+        }
+        C[off] = re;
+        C[off + g.c_plane] = im;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA contraction kernel (gfx950): complex C = A B as four real products per
+// 16x16x4 MFMA tile (Ar Br - Ai Bi, Ar Bi + Ai Br).  The matrix-core operands
+// are fed transposed (B^T as the first, A^T as the second) so that the output
+// lanes of each 16x16 tile run along m, the contiguous index of C.  Tiles of A
+// (BM x 16) and B (16 x BN) are staged through LDS; the next k-tile is fetched
+// into registers while the current one is multiplied.  A k-tile never crosses
+// a boundary of the outer contraction index (Kin % 16 == 0).
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MfmaT;
+template <>
+struct MfmaT<float> {
+    typedef f32x4 acc_t;
+    static __device__ inline acc_t mfma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // row of register r of lane l inside the 16x16 output tile
+    static __device__ inline int row(int l, int r) { return 4 * (l / 16) + r; }
+    static constexpr int PAD = 16;
+};
+template <>
+struct MfmaT<double> {
+    typedef f64x4 acc_t;
+    static __device__ inline acc_t mfma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int l, int r) { return (l / 16) + 4 * r; }
+    static constexpr int PAD = 8;
+};
+
+template <typename R, int BM, int BN, bool AK, bool BKF>
+__global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, int tilesN, int splits,
+                                                       int kchunk, R* partial) {
+    if (g.skip && *g.skip) return;
+    constexpr int BK = 16;
+    constexpr int WM = BM / 2, WN = BN / 2;      // 2 x 2 waves
+    constexpr int TI = WM / 16, TJ = WN / 16;    // 16 x 16 tiles per wave
+    constexpr int PAD = MfmaT<R>::PAD;
+    constexpr int QA = BM * BK / 256, QB = BN * BK / 256;
+    typedef typename MfmaT<R>::acc_t acc_t;
+    // double-buffered k-tiles: [buffer][plane][k][index]
+    __shared__ R As[2][2][BK][BM + PAD];
+    __shared__ R Bs[2][2][BK][BN + PAD];
+    int64_t bid = blockIdx.x;
+    const int tm = bid % tilesM;
+    bid /= tilesM;
+    const int tn = bid % tilesN;
+    bid /= tilesN;
+    const int sp = bid % splits;
+    bid /= splits;
+    const int b = (int)bid;
+    const int b1 = b % g.B1, b2 = b / g.B1;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const R* A = g.A + b1 * g.sab1 + b2 * g.sab2 + (int64_t)m0 * g.sam;
+    const R* B = g.B + b1 * g.sbb1 + b2 * g.sbb2 + (int64_t)n0 * g.sbn;
+    const int K = g.Kin * g.Kout;
+    const int kb = sp * kchunk;
+    const int ke = min(K, kb + kchunk);
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wm0 = (wave % 2) * WM, wn0 = (wave / 2) * WN;
+    const R sa = g.conjA ? R(-1) : R(1), sb = g.conjB ? R(-1) : R(1);
+    const int mlim = g.M - m0, nlim = g.N - n0;
+
+    // per-thread load slots (fixed across k-tiles); rows outside the matrix
+    // read row 0 of the tile and are zeroed by a mask (no divergent branches)
+    int offA[QA], offB[QB];
+    R mA[QA], mB[QB];
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+        const int e = tid + 256 * q;
+        const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
+        const bool ok = mm < mlim;
+        mA[q] = ok ? R(1) : R(0);
+        offA[q] = (ok ? mm : 0) * (int)g.sam + kk * (int)g.sak;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        const int e = tid + 256 * q;
+        const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
+        const bool ok = nn < nlim;
+        mB[q] = ok ? R(1) : R(0);
+        offB[q] = (ok ? nn : 0) * (int)g.sbn + kk * (int)g.sbk;
+    }
+    R pa[2][QA], pb[2][QB];
+    auto fetch = [&](int k0) {
+        const int kin = k0 % g.Kin, kout = k0 / g.Kin;
+        const R* Ab = A + (int64_t)kin * g.sak + (int64_t)kout * g.sako;
+        const R* Bb = B + (int64_t)kin * g.sbk + (int64_t)kout * g.sbko;
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            pa[0][q] = mA[q] * Ab[offA[q]];
+            pa[1][q] = (sa * mA[q]) * Ab[offA[q] + g.a_plane];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            pb[0][q] = mB[q] * Bb[offB[q]];
+            pb[1][q] = (sb * mB[q]) * Bb[offB[q] + g.b_plane];
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + 256 * q;
+            const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
+            As[buf][0][kk][mm] = pa[0][q];
+            As[buf][1][kk][mm] = pa[1][q];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + 256 * q;
+            const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
+            Bs[buf][0][kk][nn] = pb[0][q];
+            Bs[buf][1][kk][nn] = pb[1][q];
+        }
+    };
+    acc_t cre[TI][TJ], cim[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            cre[i][j] = acc_t{0, 0, 0, 0};
+            cim[i][j] = acc_t{0, 0, 0, 0};
+        }
+    const int nt = (ke - kb) / BK;   // k-tiles of this split (K and kchunk are multiples of BK)
+    if (nt > 0) {
+        fetch(kb);
+        stash(0);
+        if (nt > 1) fetch(kb + BK);
+    }
+    __syncthreads();
+    for (int t = 0; t < nt; ++t) {
+        const int cur = t & 1;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + lane / 16, c16 = lane % 16;
+            R br[TJ], bi[TJ], nbi[TJ], ar[TI], ai[TI];
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+                br[j] = Bs[cur][0][kr][wn0 + 16 * j + c16];
+                bi[j] = Bs[cur][1][kr][wn0 + 16 * j + c16];
+                nbi[j] = -bi[j];
+            }
+#pragma unroll
+            for (int i = 0; i < TI; ++i) {
+                ar[i] = As[cur][0][kr][wm0 + 16 * i + c16];
+                ai[i] = As[cur][1][kr][wm0 + 16 * i + c16];
+            }
+            // output tile (j, i) holds C^T[n][m]: first operand from B, second
+            // from A; the four real products go out in two passes so that
+            // back-to-back MFMAs never share an accumulator
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) {
+                    cre[i][j] = MfmaT<R>::mfma(br[j], ar[i], cre[i][j]);
+                    cim[i][j] = MfmaT<R>::mfma(bi[j], ar[i], cim[i][j]);
+                }
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) {
+                    cre[i][j] = MfmaT<R>::mfma(nbi[j], ai[i], cre[i][j]);
+                    cim[i][j] = MfmaT<R>::mfma(br[j], ai[i], cim[i][j]);
+                }
+        }
+        // the other buffer was last read before the previous barrier
+        if (t + 1 < nt) {
+            stash(cur ^ 1);
+            if (t + 2 < nt) fetch(kb + (t + 2) * BK);
+        }
+        __syncthreads();
+    }
+    const int64_t MN = (int64_t)g.M * g.N;
+    const int nbatch = g.B1 * g.B2;
+    R* C = g.C + b1 * g.scb1 + b2 * g.scb2;
+    R* P = partial + ((int64_t)sp * nbatch + b) * 2 * MN;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm0 + 16 * i + lane % 16;
+                const int n = n0 + wn0 + 16 * j + MfmaT<R>::row(lane, r);
+                if (m >= g.M || n >= g.N) continue;
+                if (splits == 1) {
+                    const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
+                    R re = g.alpha * cre[i][j][r], im = g.alpha * cim[i][j][r];
+                    if (g.beta) {
+                        re += C[off];
+                        im += C[off + g.c_plane];
+                    }
+                    C[off] = re;
+                    C[off + g.c_plane] = im;
+                } else {
+                    P[m + (int64_t)g.M * n] = cre[i][j][r];
+                    P[MN + m + (int64_t)g.M * n] = cim[i][j][r];
+                }
+            }
+}
+
+// Largest element offset an operand can touch (all strides are >= 0).
+inline bool inside(const GemmScratch& ws, const void* base, int64_t max_off, int64_t plane, int esz) {
+    if (!ws.regions) return true;
+    const uintptr_t p = (uintptr_t)base;
+    int lo = 0, hi = ws.n_regions - 1, f = -1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) / 2;
+        if (ws.regions[mid].lo <= p) {
+            f = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (f < 0) return false;
+    const uintptr_t end = p + (uintptr_t)(max_off + plane + 1) * esz;
+    return p >= ws.regions[f].lo && end <= ws.regions[f].hi;
+}
+
+}  // namespace
+
+bool g_dry_run = false;
+
+template <typename R>
+bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen, hipEvent_t ev0,
+           hipEvent_t ev1) {
+    if (g.M <= 0 || g.N <= 0 || g.B1 * g.B2 <= 0) return true;
+    {
+        const int64_t km = g.Kin > 0 ? g.Kin - 1 : 0, ko = g.Kout > 0 ? g.Kout - 1 : 0;
+        const int64_t b1 = g.B1 - 1, b2 = g.B2 - 1;
+        const int64_t amax = (g.M - 1) * g.sam + km * g.sak + ko * g.sako + b1 * g.sab1 + b2 * g.sab2;
+        const int64_t bmax = (g.N - 1) * g.sbn + km * g.sbk + ko * g.sbko + b1 * g.sbb1 + b2 * g.sbb2;
+        const int64_t cmax = (g.M - 1) * g.scm + (g.N - 1) * g.scn + b1 * g.scb1 + b2 * g.scb2;
+        const bool neg = g.sam < 0 || g.sak < 0 || g.sako < 0 || g.sab1 < 0 || g.sab2 < 0 || g.sbn < 0 ||
+                         g.sbk < 0 || g.sbko < 0 || g.sbb1 < 0 || g.sbb2 < 0 || g.scm < 0 || g.scn < 0 ||
+                         g.scb1 < 0 || g.scb2 < 0 || g.a_plane < 0 || g.b_plane < 0 || g.c_plane < 0;
+        const char* bad = neg ? "negative stride"
+                          : !inside(ws, g.A, amax, g.a_plane, sizeof(R)) ? "operand A out of its region"
+                          : !inside(ws, g.B, bmax, g.b_plane, sizeof(R)) ? "operand B out of its region"
+                          : !inside(ws, g.C, cmax, g.c_plane, sizeof(R)) ? "operand C out of its region"
+                                                                         : nullptr;
+        if (bad) {
+            if (why)
+                snprintf(why, whylen, "%s (M=%d N=%d Kin=%d Kout=%d B=%dx%d)", bad, g.M, g.N, g.Kin, g.Kout,
+                         g.B1, g.B2);
+            return false;
+        }
+    }
+    if (g_dry_run) return true;
+    const int K = g.Kin * g.Kout;
+    const int64_t nbatch = (int64_t)g.B1 * g.B2;
+    const bool a_k = g.sak == 1 && g.sam != 1, b_k = g.sbk == 1 && g.sbn != 1;
+    // per-element offsets inside a tile are 32-bit in the MFMA kernel
+    const bool off32 = (int64_t)128 * (g.sam + g.sbn) + 16 * (g.sak + g.sbk) + g.a_plane + g.b_plane < (1LL << 31);
+    const bool mfma_ok = K >= 16 && g.Kin % 16 == 0 && g.M >= 16 && g.N >= 16 && (g.sam == 1 || g.sak == 1) &&
+                         (g.sbn == 1 || g.sbk == 1) && off32;
+    if (mfma_ok) {
+        // tile choice: large tiles when the grid still fills the chip
+        const bool big = g.M >= 128 && g.N >= (sizeof(R) == 4 ? 128 : 64);
+        const int BM = big ? 128 : 64;
+        const int BN = big ? (sizeof(R) == 4 ? 128 : 64) : 64;
+        const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
+        const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
+        int splits = 1;
+        const int ktiles = K / 16;
+        if (tiles < 256 && ktiles >= 8) {
+            splits = (int)std::min<int64_t>((512 + tiles - 1) / tiles, ktiles / 4);
+            const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
+            const int64_t cap = per > 0 ? ws.bytes / per : 1;
+            if (splits > cap) splits = (int)cap;
+            if (splits < 1) splits = 1;
+        }
+        int kchunk = K;
+        if (splits > 1) {
+            kchunk = ((ktiles + splits - 1) / splits) * 16;
+            splits = (K + kchunk - 1) / kchunk;
+        }
+        const dim3 grid((unsigned)(tiles * splits)), blk(256);
+        R* part = (R*)ws.partial;
+        if (ev0) (void)hipEventRecord(ev0, s);
+#define TTN_MFMA_LAUNCH(bm, bn)                                                                              \
+    do {                                                                                                     \
+        if (a_k && b_k)                                                                                      \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, true, true>), grid, blk, 0, s, g, tilesM, tilesN,    \
+                               splits, kchunk, part);                                                        \
+        else if (a_k)                                                                                        \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, true, false>), grid, blk, 0, s, g, tilesM, tilesN,   \
+                               splits, kchunk, part);                                                        \
+        else if (b_k)                                                                                        \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, false, true>), grid, blk, 0, s, g, tilesM, tilesN,   \
+                               splits, kchunk, part);                                                        \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, false, false>), grid, blk, 0, s, g, tilesM, tilesN,  \
+                               splits, kchunk, part);                                                        \
+    } while (0)
+        if constexpr (sizeof(R) == 4) {
+            if (BM == 128)
+                TTN_MFMA_LAUNCH(128, 128);
+            else
+                TTN_MFMA_LAUNCH(64, 64);
+        } else {
+            if (BM == 128)
+                TTN_MFMA_LAUNCH(128, 64);
+            else
+                TTN_MFMA_LAUNCH(64, 64);
+        }
+#undef TTN_MFMA_LAUNCH
+        if (ev1) (void)hipEventRecord(ev1, s);
+        if (splits > 1) {
+            const int64_t total = (int64_t)g.M * g.N * nbatch;
+            const int nb = (int)std::min<int64_t>((total + 255) / 256, 4096);
+            hipLaunchKernelGGL((k_splitk_reduce<R>), dim3(nb), dim3(256), 0, s, g, splits, (const R*)ws.partial);
+        }
+        return true;
+    }
+    constexpr int BM = 64, BN = 64, BK = 16;
+    const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
+    const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
+    int splits = 1;
+    if (K > 0 && tiles < 256 && K > 8 * BK) {
+        splits = (int)std::min<int64_t>((512 + tiles - 1) / tiles, K / (4 * BK));
+        const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
+        const int64_t cap = per > 0 ? ws.bytes / per : 1;
+        if (splits > cap) splits = (int)cap;
+        if (splits < 1) splits = 1;
+    }
+    int kchunk = K;
+    if (splits > 1) {
+        kchunk = ((K + splits - 1) / splits + BK - 1) / BK * BK;
+        splits = (K + kchunk - 1) / kchunk;
+    }
+    if (K == 0) kchunk = 0;
+    const int a_mfast = (g.sam == 1 || g.sak != 1) ? 1 : 0;
+    const int b_nfast = (g.sbn == 1 || g.sbk != 1) ? 1 : 0;
+    const int64_t blocks = tiles * splits;
+    if (ev0) (void)hipEventRecord(ev0, s);
+    hipLaunchKernelGGL((k_cgemm<R, BM, BN, BK>), dim3((unsigned)blocks), dim3(GEMM_THREADS), 0, s, g,
+                       tilesM, tilesN, splits, kchunk, (R*)ws.partial, a_mfast, b_nfast);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    if (splits > 1) {
+        const int64_t total = (int64_t)g.M * g.N * nbatch;
+        const int nb = (int)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL((k_splitk_reduce<R>), dim3(nb), dim3(256), 0, s, g, splits,
+                           (const R*)ws.partial);
+    }
+    return true;
+}
+
+template bool cgemm<double>(const Gemm<double>&, const GemmScratch&, hipStream_t, char*, int, hipEvent_t,
+                            hipEvent_t);
+template bool cgemm<float>(const Gemm<float>&, const GemmScratch&, hipStream_t, char*, int, hipEvent_t,
+                           hipEvent_t);
+
+}  // namespace ttn
