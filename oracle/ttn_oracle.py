@@ -30,11 +30,18 @@ What it computes (paper sections in brackets):
     tridiagonal exponential through its symmetric eigendecomposition.
   * Observables: GHZ fidelity F = |<GHZ|psi>|^2 [Sec. on GHZ results],
     norm [open-system section], state overlap for C(p1, p2) [Tab. conv8x8].
+  * Gradient of F with respect to the pulse table (the paper optimises
+    pulses but gives no gradient method): the exact derivative of this
+    discrete map, by reverse-mode automatic differentiation through every
+    operation above (fidelity_gradient).
 
 Parity pinned by tests/test_oracle_pins.py (dense state-vector evolution at
 maximal chi, conservation laws, closed forms, padding invariance, blockade
-limit, GHZ as a chi = 2 network).  At truncated chi the TDVP result has no
-closed form: only the invariants pin it ("parity unpinned" beyond those).
+limit, GHZ as a chi = 2 network); the gradient by tests/test_oracle_grad.py
+(the dense Frechet-derivative gradient at maximal chi, central differences
+of the map at truncated chi, exact zeros for dark atoms).  At truncated chi
+the TDVP result has no closed form: only the invariants pin it ("parity
+unpinned" beyond those).
 """
 from __future__ import annotations
 
@@ -156,7 +163,7 @@ def lanczos_expm(apply, v0, tau: float, m: int):
     beta_{j+1} <= tol (|alpha_j| + beta_j).  The exponential of the real
     symmetric tridiagonal matrix T_m comes from its eigendecomposition."""
     beta0 = torch.linalg.vector_norm(v0)
-    if float(beta0) == 0.0:
+    if float(beta0.detach()) == 0.0:
         return v0.clone(), dict(m=0, beta=[])
     V = [v0 / beta0]
     alphas: List[torch.Tensor] = []
@@ -176,7 +183,7 @@ def lanczos_expm(apply, v0, tau: float, m: int):
                 w = w - ck * Vk
         b = torch.linalg.vector_norm(w)
         bprev = betas[j - 1] if j > 0 else torch.zeros((), dtype=RDT)
-        if float(b) <= LANCZOS_BREAKDOWN * (abs(float(a)) + float(bprev)):
+        if float(b.detach()) <= LANCZOS_BREAKDOWN * (abs(float(a.detach())) + float(bprev.detach())):
             break
         betas.append(b)
         V.append(w / b)
@@ -191,7 +198,7 @@ def lanczos_expm(apply, v0, tau: float, m: int):
     out = torch.zeros_like(v0)
     for i in range(k):
         out = out + (beta0 * y[i]) * V[i]
-    return out, dict(m=k, beta=[float(b) for b in betas])
+    return out, dict(m=k, beta=[float(b.detach()) for b in betas])
 
 
 # ---------------------------------------------------------------------------
@@ -538,6 +545,10 @@ class OracleTTN:
 
     def product_overlap(self, states):
         """<phi_1 (x) ... (x) phi_N | psi> for per-site states[site] (d,)."""
+        return complex(self.product_overlap_t(states))
+
+    def product_overlap_t(self, states):
+        """The same overlap as a (differentiable) complex tensor."""
         tr = self.tree
         vec = {}
         st = torch.as_tensor(states, dtype=CDT)
@@ -549,9 +560,14 @@ class OracleTTN:
             else:
                 vl, vr = vec[tr.children[v][0]], vec[tr.children[v][1]]
             vec[v] = torch.einsum("l,r,lrp->p", vl, vr, T)
-        return complex(vec[tr.root][0])
+        return vec[tr.root][0]
 
     def ghz_fidelity(self, target_sites):
+        F, ov = self.ghz_fidelity_t(target_sites)
+        return float(F), complex(ov)
+
+    def ghz_fidelity_t(self, target_sites):
+        """F = |<GHZ_S|psi>|^2 and the overlap, as tensors."""
         N, d = self.tree.N, self.d
         zero = torch.zeros(N, d, dtype=CDT)
         zero[:, 0] = 1.0
@@ -559,8 +575,8 @@ class OracleTTN:
         for s in target_sites:
             one[int(s), 0] = 0.0
             one[int(s), 1] = 1.0
-        ov = (self.product_overlap(zero) + self.product_overlap(one)) / math.sqrt(2.0)
-        return abs(ov) ** 2, ov
+        ov = (self.product_overlap_t(zero) + self.product_overlap_t(one)) / math.sqrt(2.0)
+        return ov.abs() ** 2, ov
 
     def local_expectation(self, site, op):
         """<psi|O_site|psi> by contracting the network with O on one leaf."""
@@ -618,7 +634,7 @@ def build(w) -> OracleTTN:
 
 
 def run(w, n_steps: Optional[int] = None, st: Optional[OracleTTN] = None, step0: int = 0,
-        record=True, apply_final_events=True):
+        record=True, apply_final_events=True, omega=None, delta=None):
     """TDVP time evolution of the workload.  Step n: apply the gate events
     scheduled at n, freeze H at t_n + dt/2, rebuild the up environments,
     then S(dt/2) and S*(dt/2).  Events scheduled at the final step count are
@@ -627,8 +643,8 @@ def run(w, n_steps: Optional[int] = None, st: Optional[OracleTTN] = None, step0:
         st = build(w)
     n_steps = w.n_steps if n_steps is None else n_steps
     edges = torch.as_tensor(w.seg_edges, dtype=RDT)
-    om = torch.as_tensor(w.omega, dtype=RDT)
-    de = torch.as_tensor(w.delta, dtype=RDT)
+    om = torch.as_tensor(w.omega, dtype=RDT) if omega is None else omega
+    de = torch.as_tensor(w.delta, dtype=RDT) if delta is None else delta
     recs = []
     tau = w.dt / 2
     for n in range(step0, step0 + n_steps):
@@ -647,3 +663,17 @@ def run(w, n_steps: Optional[int] = None, st: Optional[OracleTTN] = None, step0:
             if k == end:
                 st.apply_gate(s, U)
     return st, recs
+
+
+def fidelity_gradient(w, n_steps: Optional[int] = None, target_sites=None):
+    """dF/dOmega and dF/dDelta of the discrete TDVP map: F = |<GHZ_S|psi_n>|^2
+    after n_steps steps of run(), differentiated with respect to the pulse
+    table (site-major [N][n_seg]) by reverse-mode automatic differentiation
+    through every operation of the oracle (Lanczos, QR with the phase fix,
+    environments, gates).  Returns (F, grad_omega, grad_delta) as numpy."""
+    om = torch.tensor(w.omega, dtype=RDT, requires_grad=True)
+    de = torch.tensor(w.delta, dtype=RDT, requires_grad=True)
+    st, _ = run(w, n_steps=n_steps, record=False, omega=om, delta=de)
+    F, _ = st.ghz_fidelity_t(w.target_sites if target_sites is None else target_sites)
+    F.backward()
+    return float(F), om.grad.detach().numpy().copy(), de.grad.detach().numpy().copy()
