@@ -144,10 +144,35 @@ int ttn_overlap(ttn_handle* a, ttn_handle* b, double out[2]);
  * of complex elements needed when host == NULL. */
 int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len);
 
-/* Gradient of the fidelity with respect to the pulse table (reverse mode
- * through the discrete evolution).  Not available in this build:
- * returns TTN_ENOTSUP. */
-int ttn_backward(ttn_handle* h, double dF, double* grad_omega, double* grad_delta);
+/* Reverse mode (gradient of the fidelity with respect to the pulse table).
+ * The paper optimises pulses by simulation but states no gradient method;
+ * the gradient here is the exact derivative of the discrete map the forward
+ * path computes, by reverse-mode differentiation of every operation of the
+ * steps (gauge moves, environment builds, Lanczos exponentials with the
+ * Frechet derivative of the exponential by Gauss-Legendre quadrature).
+ *
+ * ttn_adjoint_query: device bytes of the adjoint buffer for recording
+ * n_steps steps with a checkpoint every ckpt_every (>= 1) steps:
+ * ceil(n_steps / ckpt_every) + ckpt_every + 1 network states, the adjoint
+ * scratch and the tape of one step.  TTN_EINVAL for a bad config. */
+int ttn_adjoint_query(const ttn_config* cfg, int32_t n_steps, int32_t ckpt_every, size_t* device_bytes);
+
+/* Starts recording at the current state: the gate events of the current
+ * step count are applied now, and the next n_steps TDVP steps store
+ * checkpoints in d_buf (caller-owned device memory of at least the queried
+ * size, which must outlive the recording; TTN_ENOMEM if it is smaller).  A
+ * later ttn_set_pulses ends the recording; steps beyond n_steps invalidate
+ * it. */
+int ttn_record_begin(ttn_handle* h, int32_t n_steps, int32_t ckpt_every, void* d_buf, size_t bytes);
+
+/* grad_omega, grad_delta (host [N][n_seg], overwritten) = dF * dF/dOmega,
+ * dF * dF/dDelta for F = |<GHZ_S|psi>|^2 at the current state (S =
+ * target_sites, as in ttn_fidelity), through every step recorded since
+ * ttn_record_begin.  The steps are recomputed from the checkpoints with a
+ * tape and reversed; the state is left as it was.  TTN_ESTATE without a
+ * valid recording. */
+int ttn_backward(ttn_handle* h, int32_t n_target, const int32_t* target_sites, double dF, double* grad_omega,
+                 double* grad_delta);
 
 /* The tensor-product-operator contraction on one leg of node tensors
  * (Sec. "Tensor network simulations": each term of the Hamiltonian acts on
@@ -193,8 +218,9 @@ int ttn_profile_end(ttn_handle* h, ttn_profile* out);
 
 /* Checks the launch plan of a configuration without a device: walks
  * initialisation, n_steps TDVP steps of a one-segment program with a gate on
- * every site, the fidelity, a local expectation and a self overlap, and
- * verifies that every kernel operand stays inside its workspace allocation.
+ * every site (recorded for the adjoint), the fidelity, a local expectation,
+ * a self overlap and the backward pass, and verifies that every kernel
+ * operand stays inside its workspace or adjoint-buffer allocation.
  * No device memory is touched.  msg (may be NULL) receives "ok" or the first
  * violation.  Not thread safe with concurrent device calls of this library. */
 int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t msg_len);

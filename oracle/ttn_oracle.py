@@ -676,4 +676,4 @@ def fidelity_gradient(w, n_steps: Optional[int] = None, target_sites=None):
     st, _ = run(w, n_steps=n_steps, record=False, omega=om, delta=de)
     F, _ = st.ghz_fidelity_t(w.target_sites if target_sites is None else target_sites)
     F.backward()
-    return float(F), om.grad.detach().numpy().copy(), de.grad.detach().numpy().copy()
+    return float(F.detach()), om.grad.detach().numpy().copy(), de.grad.detach().numpy().copy()

@@ -53,6 +53,8 @@ struct Bump {
     }
 };
 
+struct AdjState;   // reverse-mode state (adjoint.inc)
+
 struct Event {
     int step, site;
     double* U;   // device, d x d planar column-major
@@ -121,6 +123,8 @@ struct ttn_handle {
     };
     std::vector<ProfRec> prof_recs;
     int64_t prof_matvecs = 0;
+    // reverse mode (checkpoints, tape, adjoints); null until recording starts
+    AdjState* adj = nullptr;
 };
 
 namespace {
@@ -402,7 +406,7 @@ void leg_apply(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int64_t 
 // stride sx) -- one GEMM with a two-level contraction index.
 template <typename R>
 void leg_apply_sum(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int64_t sx, R* Y, int DL,
-                   int DR, int DP, int cnt, int beta) {
+                   int DR, int DP, int cnt, int beta, bool conj = false, bool trans = false) {
     if (cnt <= 0) return;
     const int64_t n = (int64_t)DL * DR * DP;
     Gemm<R> g;
@@ -423,9 +427,10 @@ void leg_apply_sum(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int6
         g.sab1 = (int64_t)DL * DR;
         g.B = Op;
         g.b_plane = (int64_t)D * D;
-        g.sbk = D;
-        g.sbn = 1;
+        g.sbk = trans ? 1 : D;
+        g.sbn = trans ? D : 1;
         g.sbko = so;
+        g.conjB = conj;
         g.C = Y;
         g.c_plane = n;
         g.scm = 1;
@@ -443,9 +448,10 @@ void leg_apply_sum(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int6
         g.sako = sx;
         g.B = Op;
         g.b_plane = (int64_t)D * D;
-        g.sbk = D;
-        g.sbn = 1;
+        g.sbk = trans ? 1 : D;
+        g.sbn = trans ? D : 1;
         g.sbko = so;
+        g.conjB = conj;
         g.C = Y;
         g.c_plane = n;
         g.scm = 1;
@@ -458,9 +464,10 @@ void leg_apply_sum(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int6
         g.Kin = D;
         g.A = Op;
         g.a_plane = (int64_t)D * D;
-        g.sam = 1;
-        g.sak = D;
+        g.sam = trans ? D : 1;
+        g.sak = trans ? 1 : D;
         g.sako = so;
+        g.conjA = conj;
         g.B = X;
         g.b_plane = n;
         g.sbk = 1;
@@ -474,24 +481,29 @@ void leg_apply_sum(Ctx<R>& c, int leg, const R* Op, int64_t so, const R* X, int6
     c.run(g);
 }
 
-// E_k[a, b] = sum over the other legs of conj(Q[.., a, ..]) X_k[.., b, ..]
-// for nx tensors X_k (stride sx); outputs D x D column-major (stride se).
+// E_k[a, b] = alpha sum over the other legs of opA(A_k[.., a, ..]) opB(B_k[.., b, ..])
+// (+ E_k if beta) for nb pairs (A stride sa, B stride sb: 0 for a shared
+// tensor); opX conjugates when conjX.  Outputs D x D column-major, stride se.
 template <typename R>
-void leg_gram(Ctx<R>& c, int leg, const R* Q, const R* X, int64_t sx, R* E, int64_t se, int DL, int DR, int DP,
-              int nx) {
+void leg_gram_gen(Ctx<R>& c, int leg, const R* A, int64_t sa, bool conjA, const R* B, int64_t sb, bool conjB,
+                  R* E, int64_t se, int DL, int DR, int DP, int nb, int beta = 0, R alpha = 1) {
     const int64_t n = (int64_t)DL * DR * DP;
     Gemm<R> g;
     g.skip = c.skip;
-    g.conjA = true;
-    g.A = Q;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.conjA = conjA;
+    g.conjB = conjB;
+    g.A = A;
     g.a_plane = n;
-    g.B = X;
+    g.sab1 = sa;
+    g.B = B;
     g.b_plane = n;
-    g.sbb1 = sx;
+    g.sbb1 = sb;
     g.C = E;
     g.scm = 1;
     g.scb1 = se;
-    g.B1 = nx;
+    g.B1 = nb;
     if (leg == 2) {
         const int D = DP;
         g.M = g.N = D;
@@ -529,15 +541,24 @@ void leg_gram(Ctx<R>& c, int leg, const R* Q, const R* X, int64_t sx, R* E, int6
     c.run(g);
 }
 
+// E_k[a, b] = sum over the other legs of conj(Q[.., a, ..]) X_k[.., b, ..]
+// for nx tensors X_k (stride sx); outputs D x D column-major (stride se).
+template <typename R>
+void leg_gram(Ctx<R>& c, int leg, const R* Q, const R* X, int64_t sx, R* E, int64_t se, int DL, int DR, int DP,
+              int nx) {
+    leg_gram_gen<R>(c, leg, Q, 0, true, X, sx, false, E, se, DL, DR, DP, nx);
+}
+
 // A stack: out slot i = sum_j V[i][j] N_j for the operator stack Nstk (slots
 // 1..ns of a [H, N_1..] stack with matrices D x D), V given as a planar
 // (ni x ns) matrix in column-major j + ns*i (i.e. V^T col-major).
 void vsum_stack(Ctx<double>& c, const double* Nstk, int D, int ns, const double* Vt, int ni,
-                double* out_slot1) {
+                double* out_slot1, int beta = 0) {
     if (ni <= 0 || ns <= 0) return;
     const int64_t D2 = (int64_t)D * D;
     Gemm<double> g;
     g.skip = c.skip;
+    g.beta = beta;
     g.M = (int)D2;
     g.N = ni;
     g.Kin = ns;
@@ -672,7 +693,9 @@ void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, c
 }
 
 // x <- exp(-i tau Op) x by Lanczos (full re-orthogonalisation, device scalars)
-void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
+// Krylov basis of Op from x (full re-orthogonalisation, device scalars):
+// h->Vk holds the basis, h->lz the tridiagonal projection and ||x||.
+void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
     const int nb = (int)std::min<int64_t>(RED_BLOCKS, (n + 255) / 256);
     hipStream_t s = h->stream;
@@ -696,15 +719,24 @@ void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
         lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s);
         lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s);
     }
-    lz_expm(lz, tau, h->st, s);
-    lz_combine(h->Vk, n, x, lz, s);
+}
+
+// x <- exp(-i tau Op) x by Lanczos
+void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
+    const int64_t n = (int64_t)o.DL * o.DR * o.DP;
+    lanczos_basis(h, o, x);
+    lz_expm(h->lz, tau, h->st, h->stream);
+    lz_combine(h->Vk, n, x, h->lz, h->stream);
 }
 
 // ---------------------------------------------------------------------------
 // QR gauge move (CholeskyQR2): T[.., a, ..] = sum_k Q[.., k, ..] R[k, a]
 // with R upper triangular, real positive diagonal; Q overwrites T, R -> Rout.
 // ---------------------------------------------------------------------------
-void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, double* Rout) {
+// With rinvh != nullptr also writes R^{-H} = L2^{-1} L1^{-1} (for the adjoint),
+// keeping L1^{-1} in l1inv (D x D scratch).
+void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, double* Rout,
+               double* rinvh = nullptr, double* l1inv = nullptr) {
     Ctx<double> c{h, nullptr};
     const int D = leg == 0 ? DL : (leg == 1 ? DR : DP);
     const int64_t n = (int64_t)DL * DR * DP;
@@ -718,10 +750,33 @@ void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, doubl
     chk(h, h->cholwork, (int64_t)D * (D + 1) + 2 * (int64_t)D * 16, "cholesky work");
     leg_gram(c, leg, Tv, Tv, 0, h->G, 0, DL, DR, DP, 1);
     chol_inv(h->G, D, h->Linv, h->R1, nullptr, h->cholwork, h->st, h->stream);
+    if (rinvh) {
+        chk(h, l1inv, 2 * (int64_t)D * D, "L1 inverse");
+        copy_d(h->Linv, l1inv, 2 * (int64_t)D * D, nullptr, h->stream);
+    }
     leg_apply<double>(c, leg, h->Linv, 0, Tv, 0, h->Qtmp, 0, DL, DR, DP, 1, 0, true, false);
     leg_gram(c, leg, h->Qtmp, h->Qtmp, 0, h->G, 0, DL, DR, DP, 1);
     chol_inv(h->G, D, h->Linv, h->R2, nullptr, h->cholwork, h->st, h->stream);
     leg_apply<double>(c, leg, h->Linv, 0, h->Qtmp, 0, Tv, 0, DL, DR, DP, 1, 0, true, false);
+    if (rinvh) {
+        chk(h, rinvh, 2 * (int64_t)D * D, "R^-H");
+        Gemm<double> gi;
+        gi.M = gi.N = D;
+        gi.Kin = D;
+        gi.A = h->Linv;
+        gi.a_plane = (int64_t)D * D;
+        gi.sam = 1;
+        gi.sak = D;
+        gi.B = l1inv;
+        gi.b_plane = (int64_t)D * D;
+        gi.sbk = 1;
+        gi.sbn = D;
+        gi.C = rinvh;
+        gi.c_plane = (int64_t)D * D;
+        gi.scm = 1;
+        gi.scn = D;
+        c.run(gi);
+    }
     // R = R2 R1 (both upper triangular, D x D column-major)
     Gemm<double> g;
     g.M = g.N = D;
@@ -1293,6 +1348,12 @@ void check_step_flags(ttn_handle* h, StepDev* out) {
     if (s.bad) throw StatusError{TTN_ENUMERIC, "non-positive pivot in a QR gauge move (rank-deficient node)"};
 }
 
+#include "adjoint.inc"
+
+// A device-free handle for plan checks: workspace carved at a fake address,
+// the initial network built and a one-segment program with a gate on every site.
+ttn_handle* make_dry_handle(const ttn_config* cfg, size_t bytes);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1362,6 +1423,7 @@ int ttn_set_pulses(ttn_handle* h, int32_t n_seg, const double* seg_edges, const 
                    const double* ev_u) {
     if (!h) return TTN_EINVAL;
     if (h->poisoned) return TTN_ESTATE;
+    if (h->adj) h->adj->active = false;   // a recording is tied to one pulse table
     try {
         if (n_seg < 0 || (n_seg > 0 && (!seg_edges || !omega || !delta)) || n_events < 0 ||
             (n_events > 0 && (!ev_step || !ev_site || !ev_u)))
@@ -1449,11 +1511,13 @@ int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* sta
         for (int i = 0; i < n_steps; ++i) {
             reset_step_dev(h);
             apply_events_at(h, h->step_count);
+            record_step_start(h);
             const double t = ((double)h->step_count + 0.5) * dt;
             set_hamiltonian(h, segment_at(h, t));
             rebuild_up(h);
             sweep_fwd(h, dt / 2);
             sweep_bwd(h, dt / 2);
+            record_step_end(h);
             h->step_count += 1;
             if (stats) {
                 StepDev s;
@@ -1704,26 +1768,14 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         size_t bytes = 0;
         int rc = ttn_workspace_query(cfg, &bytes);
         if (rc != TTN_OK) return rc;
-        h = new ttn_handle();
-        h->dry = true;
         g_dry_run = true;
-        setup_config(h, cfg);
-        void* fake = (void*)(uintptr_t(1) << 44);
-        Bump b(fake, bytes, &h->regions);
-        plan(h, b);
-        sort_regions(h);
-        build_couplings(h, cfg->pos_xy);
-        initial_tensors(h, cfg);
-        canonicalise(h);
-        // a program with one segment and one gate event on every leaf
+        h = make_dry_handle(cfg, bytes);
         const int N = h->N, d = h->d;
-        std::vector<double> edges = {0.0, 1e9}, om(N, 1.0), de(N, 0.5), u((size_t)N * 2 * d * d, 0.0);
-        std::vector<int32_t> st(N, 0), site(N);
-        for (int i = 0; i < N; ++i) {
-            site[i] = i;
-            for (int a = 0; a < d; ++a) u[(size_t)i * 2 * d * d + 2 * (a * d + a)] = 1.0;
-        }
-        rc = ttn_set_pulses(h, 1, edges.data(), om.data(), de.data(), N, st.data(), site.data(), u.data());
+        // record the steps for the adjoint, then walk the backward pass too
+        const int32_t k = std::max(1, n_steps / 2);
+        const size_t abytes = adjoint_bytes(h, n_steps, k);
+        void* afake = (void*)(uintptr_t(1) << 45);
+        rc = ttn_record_begin(h, n_steps, k, afake, abytes);
         if (rc != TTN_OK) throw StatusError{rc, h->err};
         std::vector<ttn_step_stats> stats(std::max(1, n_steps));
         rc = ttn_tdvp_step(h, 0.01, n_steps, stats.data());
@@ -1738,34 +1790,92 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         if (rc != TTN_OK) throw StatusError{rc, h->err};
         rc = ttn_overlap(h, h, ov);
         if (rc != TTN_OK) throw StatusError{rc, h->err};
+        std::vector<double> go((size_t)N * h->n_seg), gd((size_t)N * h->n_seg);
+        rc = ttn_backward(h, N, all.data(), 1.0, go.data(), gd.data());
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
         g_dry_run = false;
         report("ok");
-        delete h;
+        ttn_destroy(h);
         return TTN_OK;
     } catch (const StatusError& e) {
         g_dry_run = false;
         report(e.msg);
-        delete h;
+        if (h) ttn_destroy(h);
         return e.code;
     } catch (...) {
         g_dry_run = false;
         report("unexpected exception");
-        delete h;
+        if (h) ttn_destroy(h);
         return TTN_EINVAL;
     }
 }
 
-int ttn_backward(ttn_handle* h, double dF, double* grad_omega, double* grad_delta) {
-    (void)dF;
-    (void)grad_omega;
-    (void)grad_delta;
+int ttn_adjoint_query(const ttn_config* cfg, int32_t n_steps, int32_t ckpt_every, size_t* device_bytes) {
+    if (!cfg || !device_bytes || n_steps < 0 || ckpt_every < 1) return TTN_EINVAL;
+    ttn_handle* h = nullptr;
+    try {
+        validate(cfg);
+        size_t bytes = 0;
+        int rc = ttn_workspace_query(cfg, &bytes);
+        if (rc != TTN_OK) return rc;
+        g_dry_run = true;
+        h = make_dry_handle(cfg, bytes);
+        *device_bytes = adjoint_bytes(h, n_steps, ckpt_every);
+        g_dry_run = false;
+        ttn_destroy(h);
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        g_dry_run = false;
+        g_init_error = e.msg;
+        if (h) ttn_destroy(h);
+        return e.code;
+    } catch (...) {
+        g_dry_run = false;
+        g_init_error = "unexpected exception";
+        if (h) ttn_destroy(h);
+        return TTN_EINVAL;
+    }
+}
+
+int ttn_record_begin(ttn_handle* h, int32_t n_steps, int32_t ckpt_every, void* d_buf, size_t bytes) {
     if (!h) return TTN_EINVAL;
-    h->err = "ttn_backward is not available in this build";
-    return TTN_ENOTSUP;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (!h->d_omega && !h->dry) throw StatusError{TTN_ESTATE, "ttn_set_pulses must be called first"};
+        record_begin(h, n_steps, ckpt_every, d_buf, bytes);
+        if (!h->dry) HIPCHECK(hipGetLastError());
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_backward(ttn_handle* h, int32_t n_target, const int32_t* target_sites, double dF, double* grad_omega,
+                 double* grad_delta) {
+    if (!h || !grad_omega || !grad_delta) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (!h->adj || !h->adj->active) throw StatusError{TTN_ESTATE, "no recording (call ttn_record_begin)"};
+        if (h->adj->overflow) throw StatusError{TTN_ESTATE, "more steps taken than the recording declared"};
+        if (n_target < 0 || (n_target > 0 && !target_sites)) throw StatusError{TTN_EINVAL, "bad target"};
+        std::vector<char> in(h->N, 0);
+        for (int i = 0; i < n_target; ++i) {
+            if (target_sites[i] < 0 || target_sites[i] >= h->N) throw StatusError{TTN_EINVAL, "bad target site"};
+            in[target_sites[i]] = 1;
+        }
+        reset_step_dev(h);
+        backward(h, in, dF, grad_omega, grad_delta);
+        check_step_flags(h, nullptr);
+        if (!h->dry) HIPCHECK(hipGetLastError());
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
 }
 
 int ttn_destroy(ttn_handle* h) {
     if (!h) return TTN_EINVAL;
+    delete h->adj;
     if (!h->dry) {
         if (h->stream) (void)hipStreamSynchronize(h->stream);
         for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -1783,3 +1893,36 @@ const char* ttn_last_error(const ttn_handle* h) {
 }
 
 }  // extern "C"
+
+namespace {
+
+ttn_handle* make_dry_handle(const ttn_config* cfg, size_t bytes) {
+    ttn_handle* h = new ttn_handle();
+    try {
+        h->dry = true;
+        setup_config(h, cfg);
+        void* fake = (void*)(uintptr_t(1) << 44);
+        Bump b(fake, bytes, &h->regions);
+        plan(h, b);
+        sort_regions(h);
+        build_couplings(h, cfg->pos_xy);
+        initial_tensors(h, cfg);
+        canonicalise(h);
+        const int N = h->N, d = h->d;
+        std::vector<double> edges = {0.0, 1e9}, om(N, 1.0), de(N, 0.5), u((size_t)N * 2 * d * d, 0.0);
+        std::vector<int32_t> st(N, 0), site(N);
+        for (int i = 0; i < N; ++i) {
+            site[i] = i;
+            for (int a = 0; a < d; ++a) u[(size_t)i * 2 * d * d + 2 * (a * d + a)] = 1.0;
+        }
+        const int rc = ttn_set_pulses(h, 1, edges.data(), om.data(), de.data(), N, st.data(), site.data(), u.data());
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        return h;
+    } catch (...) {
+        ttn_destroy(h);
+        throw;
+    }
+}
+
+}  // namespace
+

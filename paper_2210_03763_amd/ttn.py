@@ -69,7 +69,9 @@ def lib():
             "ttn_local_expectation": (C.c_int, [P, I32, DP, DP]),
             "ttn_overlap": (C.c_int, [P, P, DP]),
             "ttn_export_state": (I64, [P, DP, I64]),
-            "ttn_backward": (C.c_int, [P, D, DP, DP]),
+            "ttn_adjoint_query": (C.c_int, [C.POINTER(Config), I32, I32, C.POINTER(C.c_size_t)]),
+            "ttn_record_begin": (C.c_int, [P, I32, I32, P, C.c_size_t]),
+            "ttn_backward": (C.c_int, [P, I32, IP, D, DP, DP]),
             "ttn_destroy": (C.c_int, [P]),
             "ttn_last_error": (C.c_char_p, [P]),
         }
@@ -200,6 +202,28 @@ class TTN:
         out = np.zeros(2)
         self._check(lib().ttn_overlap(self.h, other.h, _dptr(out)), self.h)
         return complex(out[0], out[1])
+
+    def record(self, n_steps: int, ckpt_every: int = 10):
+        """Start recording the next n_steps steps for backward()."""
+        import torch
+        cfg = make_config(self.w, self._keep)
+        nbytes = C.c_size_t(0)
+        self._check(lib().ttn_adjoint_query(C.byref(cfg), int(n_steps), int(ckpt_every), C.byref(nbytes)), None)
+        self.adj_buffer = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        rc = lib().ttn_record_begin(self.h, int(n_steps), int(ckpt_every), C.c_void_p(self.adj_buffer.data_ptr()),
+                                    nbytes)
+        self._check(rc, self.h)
+        return int(nbytes.value)
+
+    def backward(self, target_sites=None, dF: float = 1.0):
+        """dF * (dF/dOmega, dF/dDelta), each [N][n_seg], through the recorded steps."""
+        ts = np.ascontiguousarray(self.w.target_sites if target_sites is None else target_sites, dtype=np.int32)
+        ns = int(np.asarray(self._pulses[1]).shape[1])
+        go = np.zeros((self.w.n_sites, ns))
+        gd = np.zeros((self.w.n_sites, ns))
+        rc = lib().ttn_backward(self.h, len(ts), _iptr(ts), float(dF), _dptr(go), _dptr(gd))
+        self._check(rc, self.h)
+        return go, gd
 
     def export_state(self) -> np.ndarray:
         n = lib().ttn_export_state(self.h, None, 0)

@@ -20,7 +20,8 @@ def _declared():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for n in ("ttn_init", "ttn_set_pulses", "ttn_tdvp_step", "ttn_fidelity", "ttn_backward"):
+    for n in ("ttn_init", "ttn_set_pulses", "ttn_tdvp_step", "ttn_fidelity", "ttn_backward",
+              "ttn_adjoint_query", "ttn_record_begin"):
         assert n in names
 
 
@@ -63,7 +64,8 @@ def test_null_handle_calls():
     L = T.lib()
     assert L.ttn_tdvp_step(None, 0.01, 1, None) == T.TTN_EINVAL
     assert L.ttn_destroy(None) == T.TTN_EINVAL
-    assert L.ttn_backward(None, 1.0, None, None) == T.TTN_EINVAL
+    assert L.ttn_backward(None, 0, None, 1.0, None, None) == T.TTN_EINVAL
+    assert L.ttn_record_begin(None, 1, 1, None, 0) == T.TTN_EINVAL
 
 
 def _validate(w, n_steps=1):
@@ -96,3 +98,24 @@ def test_launch_plan_stays_in_bounds(case):
     name, mk = case
     rc, msg = _validate(mk(), 2)
     assert rc == T.TTN_OK, (name, msg)
+
+
+def test_adjoint_query_sizes():
+    from paper_2210_03763_amd import workload as W
+    keep = []
+    w = W.config("c1-ent")
+    cfg = T.make_config(w, keep)
+    import ctypes as C
+    out = [C.c_size_t(0) for _ in range(3)]
+    L = T.lib()
+    assert L.ttn_adjoint_query(C.byref(cfg), 20, 10, C.byref(out[0])) == T.TTN_OK
+    assert L.ttn_adjoint_query(C.byref(cfg), 20, 1, C.byref(out[1])) == T.TTN_OK
+    assert L.ttn_adjoint_query(C.byref(cfg), 40, 10, C.byref(out[2])) == T.TTN_OK
+    state = sum(16 * a * b * c for (a, b, c) in [(3, 3, 9)] * 8 + [(9, 9, 16)] * 4 + [(16, 16, 16)] * 2
+                + [(16, 16, 1)])
+    state = (state + 255) // 256 * 256     # every buffer is 256-byte aligned
+    # 20 checkpoints + 1 slot vs 2 checkpoints + 10 slots: 9 states apart
+    assert out[1].value - out[0].value == 9 * state
+    assert out[2].value - out[0].value == 2 * state
+    assert L.ttn_adjoint_query(C.byref(cfg), 20, 0, C.byref(out[0])) == T.TTN_EINVAL
+

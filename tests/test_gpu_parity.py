@@ -133,14 +133,6 @@ def test_observables_and_local_expectation():
     g2.close()
 
 
-def test_backward_not_supported_yet():
-    w = W.config("c1-ent").copy(n_steps=1)
-    g = T.TTN(w)
-    rc = T.lib().ttn_backward(g.h, 1.0, None, None)
-    assert rc == T.TTN_ENOTSUP
-    g.close()
-
-
 def test_undressed_rank_deficient_state_reports_enumeric():
     # an undressed product state is rank deficient above its Schmidt rank:
     # the CholeskyQR2 gauge move reports it instead of producing garbage
