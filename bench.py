@@ -8,7 +8,9 @@ bounded sample.  Prints one JSON line.
 A step is one full TDVP step (S(dt/2) then S*(dt/2) over all 63 nodes and 62
 bonds, environment refresh and program events) of the GHZ-preparation
 program; inputs are synthetic and seeded and already resident on the device
-when the timed region starts.
+when the timed region starts.  The timed steps replay the captured step
+graph; the contraction-kernel timings come from the same number of steps
+right after them, launched eagerly inside a profiling window.
 """
 from __future__ import annotations
 
@@ -129,8 +131,8 @@ def cpu_baseline(w, flops_per_step, budget_s=30.0):
 
 def calibration_copy(mib):
     """A streaming kernel of known traffic (reads and writes mib MiB once),
-    run just before the timed steps so that hardware-counter passes can
-    scale their byte counts and tell the timed dispatches apart."""
+    run just before the profiled steps so that hardware-counter passes can
+    scale their byte counts and tell those dispatches apart."""
     import torch
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -143,6 +145,10 @@ def calibration_copy(mib):
 
 
 def run_gpu(w, steps, warmup, profile=True, calib_mib=0):
+    """Warm-up steps (the first captures the step graph), `steps` timed steps
+    replayed from the graph, then -- with profile -- `steps` more steps in a
+    profiling window (launched eagerly, each contraction bracketed by HIP
+    events on the handle's stream)."""
     import torch
     from paper_2210_03763_amd import ttn
     L = ttn.lib()
@@ -152,20 +158,25 @@ def run_gpu(w, steps, warmup, profile=True, calib_mib=0):
     if warmup:
         g.step(warmup)
     torch.cuda.synchronize()
-    if calib_mib > 0:
-        calibration_copy(calib_mib)
-    if profile:
-        assert L.ttn_profile_begin(g.h) == 0
     t0 = time.perf_counter()
     g.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = Profile()
+    ms_prof = None
     if profile:
+        if calib_mib > 0:
+            calibration_copy(calib_mib)
+        assert L.ttn_profile_begin(g.h) == 0
+        t2 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
         assert L.ttn_profile_end(g.h, C.byref(prof)) == 0
+        ms_prof = (t3 - t2) * 1e3 / steps
     F, _ = g.fidelity()
     n2, E = g.observables()
-    return g, (t1 - t0) * 1e3 / steps, prof, F, n2, E
+    return g, (t1 - t0) * 1e3 / steps, prof, ms_prof, F, n2, E
 
 
 def run_adjoint(w, steps):
@@ -220,7 +231,8 @@ def main():
     w = W.config(args.config)
     fps = heff_flops_per_step(w)
     print(f"[bench] mixed run: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr, flush=True)
-    gm, ms_mixed, prof, F_m, n2_m, E_m = run_gpu(w, args.steps, args.warmup, calib_mib=args.calib_copy_mib)
+    gm, ms_mixed, prof, ms_prof, F_m, n2_m, E_m = run_gpu(w, args.steps, args.warmup,
+                                                          calib_mib=args.calib_copy_mib)
     print(f"[bench] mixed {ms_mixed:.1f} ms/step F={F_m:.12f}", file=sys.stderr, flush=True)
     k = prof.gemm_f32 if w.precision == ttn.PREC_FP32 else prof.gemm_f64
     dt = "fp32" if w.precision == ttn.PREC_FP32 else "fp64"
@@ -233,7 +245,9 @@ def main():
                       f"reduction): H_eff/K_eff stages and environment updates",
             "launches": int(k.launches), "avg_launch_ms": round(avg_ms, 5),
             "algorithmic_gflop_per_launch": round(k.flops / max(1, k.launches) / 1e9, 4),
-            "heff_share_of_kernel_flops": round(prof.heff.flops / max(1.0, k.flops), 4)}
+            "heff_share_of_kernel_flops": round(prof.heff.flops / max(1.0, k.flops), 4),
+            "window": f"the {args.steps} steps after the timed ones, launched eagerly inside a profiling "
+                      f"window ({ms_prof:.1f} ms/step there); kernel durations do not depend on graph replay"}
     out = {"metric": METRIC, "value": round(1e3 / ms_mixed, 4), "unit": "steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_mixed, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
@@ -247,13 +261,16 @@ def main():
     if not args.no_fp64 and w.precision == ttn.PREC_FP32:
         w64 = w.copy(precision=ttn.PREC_FP64)
         print(f"[bench] fp64 run: {args.steps} steps", file=sys.stderr, flush=True)
-        g64, ms64, prof64, F64, n2_64, E64 = run_gpu(w64, args.steps, args.warmup, profile=False)
+        g64, ms64, _, _, _, _, _ = run_gpu(w64, args.steps, args.warmup, profile=False)
+        g64.step(args.steps)                      # same step count as the mixed run
+        F64, _ = g64.fidelity()
+        n2_64, E64 = g64.observables()
         ov = gm.overlap(g64)
         out["fp64_path"] = {"ms_per_step": round(ms64, 3), "steps_per_s": round(1e3 / ms64, 4),
                             "mixed_speedup": round(ms64 / ms_mixed, 3),
                             "abs_dF": abs(F_m - F64), "state_infidelity_C": 1 - abs(ov) ** 2,
                             "abs_dnorm2": abs(n2_m - n2_64), "abs_dE": abs(E_m - E64),
-                            "after_steps": args.steps + args.warmup}
+                            "after_steps": 2 * args.steps + args.warmup}
         g64.close()
     gm.close()
     if args.adjoint_steps > 0:

@@ -216,6 +216,13 @@ int ttn_profile_begin(ttn_handle* h);
  * algorithmic flops per kernel class. */
 int ttn_profile_end(ttn_handle* h, ttn_profile* out);
 
+/* The environment rebuild and both sweeps of a step are the same launch
+ * sequence every step; by default it is captured once as a HIP graph (on a
+ * private stream) and replayed on the handle's stream.  enabled == 0 runs
+ * every launch eagerly.  Profiling windows always run eagerly (their timing
+ * events need individual launches). */
+int ttn_set_graphs(ttn_handle* h, int32_t enabled);
+
 /* Checks the launch plan of a configuration without a device: walks
  * initialisation, n_steps TDVP steps of a one-segment program with a gate on
  * every site (recorded for the adjoint), the fidelity, a local expectation,

@@ -125,6 +125,11 @@ struct ttn_handle {
     int64_t prof_matvecs = 0;
     // reverse mode (checkpoints, tape, adjoints); null until recording starts
     AdjState* adj = nullptr;
+    // the step body (environment rebuild and both sweeps) replayed as a HIP graph
+    bool use_graphs = true, graph_failed = false;
+    hipGraphExec_t step_graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    double graph_dt = 0;
 };
 
 namespace {
@@ -1001,6 +1006,8 @@ void sweep_bwd(ttn_handle* h, double tau) {
     }
 }
 
+void step_body(ttn_handle* h, double tau);
+
 void postorder(const ttn_handle* h, int v, std::vector<int>& out) {
     if (!is_bottom(h, v)) {
         postorder(h, h->ch0[v], out);
@@ -1053,6 +1060,81 @@ void rebuild_up(ttn_handle* h) {
     postorder(h, h->root, po);
     for (int v : po)
         if (v != h->root) build_up(h, v);
+}
+
+void step_body(ttn_handle* h, double tau) {
+    rebuild_up(h);
+    sweep_fwd(h, tau);
+    sweep_bwd(h, tau);
+}
+
+// Adds the device time of every recorded launch to `out`.
+void accumulate_prof(const std::vector<ttn_handle::ProfRec>& recs, const std::vector<hipEvent_t>& pool,
+                     ttn_profile* out) {
+    for (const auto& r : recs) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, pool[r.ev], pool[r.ev + 1]));
+        ttn_kernel_prof& k = r.prec ? out->gemm_f32 : out->gemm_f64;
+        k.launches += 1;
+        k.ms += ms;
+        k.flops += r.flops;
+        if (r.heff) {
+            out->heff.launches += 1;
+            out->heff.ms += ms;
+            out->heff.flops += r.flops;
+        }
+    }
+}
+
+// Captures step_body on a private stream into *exec (nullptr on failure).
+void capture_step(ttn_handle* h, double tau, hipGraphExec_t* exec) {
+    if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    const hipStream_t saved = h->stream;
+    h->stream = h->cap_stream;
+    hipGraph_t g = nullptr;
+    HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+    try {
+        step_body(h, tau);
+    } catch (...) {
+        (void)hipStreamEndCapture(h->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        h->stream = saved;
+        throw;
+    }
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    h->stream = saved;
+    if (e == hipSuccess && g) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *exec = nullptr;
+    }
+}
+
+// The step body is the same launch sequence every step (the Hamiltonian of
+// the step lives in the leaf blocks, set before it), so it is captured once
+// on a private stream and replayed on the handle's stream.  Profiling windows
+// run it eagerly (timing events recorded inside graph replays cannot be read
+// back on this runtime); a failed capture falls back to eager launches.
+void run_step_body(ttn_handle* h) {
+    const double tau = h->dt / 2;
+    if (h->dry || h->prof || !h->use_graphs || h->graph_failed) {
+        step_body(h, tau);
+        return;
+    }
+    if (!h->step_graph || h->graph_dt != h->dt) {
+        if (h->step_graph) HIPCHECK(hipGraphExecDestroy(h->step_graph));
+        h->step_graph = nullptr;
+        capture_step(h, tau, &h->step_graph);
+        if (!h->step_graph) {
+            h->graph_failed = true;
+            step_body(h, tau);
+            return;
+        }
+        h->graph_dt = h->dt;
+    }
+    HIPCHECK(hipGraphLaunch(h->step_graph, h->stream));
 }
 
 void apply_events_at(ttn_handle* h, int64_t step) {
@@ -1514,9 +1596,7 @@ int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* sta
             record_step_start(h);
             const double t = ((double)h->step_count + 0.5) * dt;
             set_hamiltonian(h, segment_at(h, t));
-            rebuild_up(h);
-            sweep_fwd(h, dt / 2);
-            sweep_bwd(h, dt / 2);
+            run_step_body(h);
             record_step_end(h);
             h->step_count += 1;
             if (stats) {
@@ -1735,19 +1815,7 @@ int ttn_profile_end(ttn_handle* h, ttn_profile* out) {
     try {
         sync(h);
         std::memset(out, 0, sizeof(*out));
-        for (const auto& r : h->prof_recs) {
-            float ms = 0.f;
-            HIPCHECK(hipEventElapsedTime(&ms, h->ev_pool[r.ev], h->ev_pool[r.ev + 1]));
-            ttn_kernel_prof& k = r.prec ? out->gemm_f32 : out->gemm_f64;
-            k.launches += 1;
-            k.ms += ms;
-            k.flops += r.flops;
-            if (r.heff) {
-                out->heff.launches += 1;
-                out->heff.ms += ms;
-                out->heff.flops += r.flops;
-            }
-        }
+        accumulate_prof(h->prof_recs, h->ev_pool, out);
         out->matvecs = h->prof_matvecs;
         h->prof = false;
         h->prof_recs.clear();
@@ -1808,6 +1876,12 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         if (h) ttn_destroy(h);
         return TTN_EINVAL;
     }
+}
+
+int ttn_set_graphs(ttn_handle* h, int32_t enabled) {
+    if (!h) return TTN_EINVAL;
+    h->use_graphs = enabled != 0;
+    return TTN_OK;
 }
 
 int ttn_adjoint_query(const ttn_config* cfg, int32_t n_steps, int32_t ckpt_every, size_t* device_bytes) {
@@ -1878,6 +1952,8 @@ int ttn_destroy(ttn_handle* h) {
     delete h->adj;
     if (!h->dry) {
         if (h->stream) (void)hipStreamSynchronize(h->stream);
+        if (h->step_graph) (void)hipGraphExecDestroy(h->step_graph);
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
         if (h->d_omega) (void)hipFree(h->d_omega);
         if (h->d_delta) (void)hipFree(h->d_delta);

@@ -69,6 +69,7 @@ def lib():
             "ttn_local_expectation": (C.c_int, [P, I32, DP, DP]),
             "ttn_overlap": (C.c_int, [P, P, DP]),
             "ttn_export_state": (I64, [P, DP, I64]),
+            "ttn_set_graphs": (C.c_int, [P, I32]),
             "ttn_adjoint_query": (C.c_int, [C.POINTER(Config), I32, I32, C.POINTER(C.c_size_t)]),
             "ttn_record_begin": (C.c_int, [P, I32, I32, P, C.c_size_t]),
             "ttn_backward": (C.c_int, [P, I32, IP, D, DP, DP]),
@@ -202,6 +203,10 @@ class TTN:
         out = np.zeros(2)
         self._check(lib().ttn_overlap(self.h, other.h, _dptr(out)), self.h)
         return complex(out[0], out[1])
+
+    def set_graphs(self, enabled: bool):
+        """Replay the step body as a HIP graph (default) or launch eagerly."""
+        self._check(lib().ttn_set_graphs(self.h, int(bool(enabled))), self.h)
 
     def record(self, n_steps: int, ckpt_every: int = 10):
         """Start recording the next n_steps steps for backward()."""
