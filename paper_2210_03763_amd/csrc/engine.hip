@@ -248,7 +248,10 @@ void plan(ttn_handle* h, Bump& b) {
     h->R2 = b.take<double>(2 * D2);
     h->Rq = b.take<double>(2 * D2);
     h->Cb = b.take<double>(2 * D2);
-    h->cholwork = b.take<double>(2 * D2 + 2 * (int64_t)h->Dmax * 16 + 64);
+    // Cholesky work: the padded inverse of the blocked kernel (2 Dp^2, Dp = 16
+    // ceil(D / 16)) for D <= 128, the panel buffers of the larger kernel above
+    const int64_t Dp = 16 * ((std::min(h->Dmax, 128) + 15) / 16);
+    h->cholwork = b.take<double>(std::max(2 * D2 + 2 * (int64_t)h->Dmax * 16, 2 * Dp * Dp) + 64);
     h->red = b.take<double>((int64_t)RED_BLOCKS * KRYLOV_MAX * 2 + 64);
     h->lz = b.take<LanczosDev>(1);
     h->lz_obs = b.take<LanczosDev>(1);
@@ -752,7 +755,8 @@ void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, doubl
     chk(h, h->R1, 2 * (int64_t)D * D, "R1");
     chk(h, h->R2, 2 * (int64_t)D * D, "R2");
     chk(h, Rout, 2 * (int64_t)D * D, "R out");
-    chk(h, h->cholwork, (int64_t)D * (D + 1) + 2 * (int64_t)D * 16, "cholesky work");
+    const int64_t Dpad = 16 * (int64_t)((D + 15) / 16);
+    chk(h, h->cholwork, D <= 128 ? 2 * Dpad * Dpad : (int64_t)D * (D + 1) + 2 * (int64_t)D * 16, "cholesky work");
     leg_gram(c, leg, Tv, Tv, 0, h->G, 0, DL, DR, DP, 1);
     chol_inv(h->G, D, h->Linv, h->R1, nullptr, h->cholwork, h->st, h->stream);
     if (rinvh) {

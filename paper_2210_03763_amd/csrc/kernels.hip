@@ -742,12 +742,350 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int 
 
 }  // namespace
 
+namespace {
+
+// Blocked Cholesky + inverse for D <= 128 in one workgroup: the lower
+// triangle in 16 x 16 blocks in LDS (36 blocks, 144 KB).  Right-looking by
+// block columns: one wave factors the diagonal block (pivots broadcast with
+// readlane, columns through LDS), the panel rows are solved by substitution
+// (one lane per row), the trailing blocks are updated with the FP64 matrix
+// cores while one wave already updates and factors the next diagonal block.
+// The inverse: every diagonal block inverted by its own wave, then the block
+// diagonals X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ, one level at a time, on
+// the matrix cores (the output fragments of one product are the B operand
+// fragments of the next).  Sizes that are not a multiple of 16 are padded
+// with an identity block.
+constexpr int CB = 16;
+constexpr int CB_MAXNB = 8;
+constexpr int CB_NBLK = CB_MAXNB * (CB_MAXNB + 1) / 2;
+constexpr int CB_THREADS = 512;
+constexpr int CB_WAVES = CB_THREADS / 64;
+
+__device__ inline int cb_bidx(int I, int J) { return I * (I + 1) / 2 + J; }
+
+__device__ inline double cb_readlane(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline void cb_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+typedef double cb_d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline cb_d4 cb_mfma(double a, double b, cb_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// O -= A B^H on a 16 x 16 block by one wave with the FP64 matrix cores.
+// Fragments: A lane l -> A[l%16][k], B lane l -> B[k][l%16], k = kk + l/16;
+// the output register r of lane l is row l/16 + 4 r, column l%16.
+__device__ inline void cb_sub_abh_mfma(const double* Ar, const double* Ai, const double* Br, const double* Bi,
+                                       double* Or, double* Oi, int lane) {
+    const int m = lane & 15, q = lane >> 4;
+    cb_d4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < CB; kk += 4) {
+        const int ia = m + CB * (kk + q);   // A[m][kk+q]; B^H[kk+q][m] = conj(B[m][kk+q])
+        const double ar = Ar[ia], ai = Ai[ia], br = Br[ia], bi = Bi[ia];
+        dr = cb_mfma(ar, br, dr);
+        dr = cb_mfma(ai, bi, dr);
+        di = cb_mfma(ai, br, di);
+        di = cb_mfma(-ar, bi, di);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = (q + 4 * r) + CB * m;
+        Or[o] -= dr[r];
+        Oi[o] -= di[r];
+    }
+}
+
+// Cholesky of the 16 x 16 Hermitian block (br, bi) in place by one wave:
+// L lower (upper zeroed); dinv[j] = 1 / L_jj to ds[0..15]; cs: 32 doubles.
+__device__ inline void cb_chol_diag(double* br, double* bi, double* ds, double* cs, int lane, int& bad) {
+    const int r = lane & 15, cg = lane >> 4;
+    double a_r[4], a_i[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        a_r[s] = br[r + CB * (4 * cg + s)];
+        a_i[s] = bi[r + CB * (4 * cg + s)];
+    }
+    double* cre = cs;
+    double* cim = cs + CB;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        const int js = j & 3, jg = j >> 2;
+        const double piv = cb_readlane(a_r[js], j + CB * jg);
+        bad |= !(piv > 1e-290);
+        const double pv = piv > 1e-290 ? piv : 1e-290;
+        double y = __builtin_amdgcn_rsq(pv);   // 1/sqrt refined by two Newton steps
+        y = y * (1.5 - 0.5 * pv * y * y);
+        y = y * (1.5 - 0.5 * pv * y * y);
+        if (lane == 0) ds[j] = y;
+        if (cg == jg) {
+            double vr = a_r[js], vi = a_i[js];
+            vr = r > j ? vr * y : (r == j ? pv * y : 0.0);
+            vi = r > j ? vi * y : 0.0;
+            a_r[js] = vr;
+            a_i[js] = vi;
+            cre[r] = vr;
+            cim[r] = vi;
+        }
+        cb_wave_sync();
+        const double lr = cre[r], li = cim[r];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int c = 4 * cg + s;
+            if (c > j) {
+                const double cr_ = cre[c], ci_ = cim[c];
+                a_r[s] -= lr * cr_ + li * ci_;
+                a_i[s] -= li * cr_ - lr * ci_;
+            }
+        }
+        cb_wave_sync();
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        br[r + CB * (4 * cg + s)] = a_r[s];
+        bi[r + CB * (4 * cg + s)] = a_i[s];
+    }
+}
+
+// X = L^{-1} of the lower block (lr_, li_) (LDS) by one wave, into global
+// (xr, xi) with leading dimension ld; ds: dinv; cs: 32 doubles scratch.
+__device__ inline void cb_inv_diag(const double* lr_, const double* li_, const double* ds, double* xr, double* xi,
+                                   int64_t ld, double* cs, int lane) {
+    const int r = lane & 15, cg = lane >> 4;
+    double x_r[4], x_i[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        x_r[s] = (r == 4 * cg + s) ? 1.0 : 0.0;
+        x_i[s] = 0.0;
+    }
+    double* rowr = cs;
+    double* rowi = cs + CB;
+#pragma unroll
+    for (int k = 0; k < CB; ++k) {
+        if (r == k) {
+            const double dk = ds[k];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                x_r[s] *= dk;
+                x_i[s] *= dk;
+                rowr[4 * cg + s] = x_r[s];
+                rowi[4 * cg + s] = x_i[s];
+            }
+        }
+        cb_wave_sync();
+        if (r > k) {
+            const double l_r = lr_[r + CB * k], l_i = li_[r + CB * k];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double xr_ = rowr[4 * cg + s], xi_ = rowi[4 * cg + s];
+                x_r[s] -= l_r * xr_ - l_i * xi_;
+                x_i[s] -= l_r * xi_ + l_i * xr_;
+            }
+        }
+        cb_wave_sync();
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        xr[r + ld * (4 * cg + s)] = x_r[s];
+        xi[r + ld * (4 * cg + s)] = x_i[s];
+    }
+}
+
+// G (D x D Hermitian, planar, column-major) = L L^H; Linv = L^{-1} (lower),
+// R = L^H (upper).  work: 2 Dp^2 doubles (Dp = 16 ceil(D / 16)).
+__global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D, double* Linv, double* R,
+                                                         double* work, StepDev* st) {
+    __shared__ double s_re[CB_NBLK * 256], s_im[CB_NBLK * 256];
+    __shared__ double s_cs[CB_WAVES * 64];
+    __shared__ double s_dinv[CB_MAXNB * CB];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int NB = (D + CB - 1) / CB, Dp = NB * CB;
+    const int64_t DD = (int64_t)D * D, P2 = (int64_t)Dp * Dp;
+    double* Xr = work;   // padded inverse, Dp x Dp column-major
+    double* Xi = work + P2;
+    double* dall = s_dinv;            // 1 / L_jj of every diagonal block, 16 per block
+    double* csw = s_cs + 64 * wave;   // per-wave scratch (32 used)
+    if (tid == 0) s_bad = 0;
+    const int nbl = NB * (NB + 1) / 2;
+    for (int b = wave; b < nbl; b += CB_WAVES) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= b) ++I;
+        const int J = b - I * (I + 1) / 2;
+        for (int rc = lane; rc < 256; rc += 64) {
+            const int r = rc & 15, c = rc >> 4, gi = CB * I + r, gj = CB * J + c;
+            const bool in = gi < D && gj < D;
+            s_re[256 * b + rc] = in ? G[gi + (int64_t)D * gj] : (gi == gj ? 1.0 : 0.0);
+            s_im[256 * b + rc] = in ? G[DD + gi + (int64_t)D * gj] : 0.0;
+        }
+    }
+    __syncthreads();
+    int bad = 0;
+    if (wave == 0) cb_chol_diag(s_re, s_im, dall, csw, lane, bad);
+    __syncthreads();
+    for (int K = 0; K < NB; ++K) {
+        const double* Lkr = s_re + 256 * cb_bidx(K, K);
+        const double* Lki = s_im + 256 * cb_bidx(K, K);
+        const double* dsum = dall + CB * K;
+        // panel: rows of A_IK (I > K) solve L_IK L_KK^H = A_IK by substitution
+        const int nrows = CB * (NB - K - 1);
+        if (tid < nrows) {
+            const int I = K + 1 + tid / CB, r = tid % CB;
+            double* ar = s_re + 256 * cb_bidx(I, K);
+            double* ai = s_im + 256 * cb_bidx(I, K);
+            double xr[CB], xi[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                double sr = ar[r + CB * c], si = ai[r + CB * c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) {   // - x_k conj(L[c][k])
+                    const double l_r = Lkr[c + CB * k], l_i = -Lki[c + CB * k];
+                    sr -= xr[k] * l_r - xi[k] * l_i;
+                    si -= xr[k] * l_i + xi[k] * l_r;
+                }
+                const double dc = dsum[c];
+                xr[c] = sr * dc;
+                xi[c] = si * dc;
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                ar[r + CB * c] = xr[c];
+                ai[r + CB * c] = xi[c];
+            }
+        }
+        __syncthreads();
+        // trailing update A_IJ -= L_IK L_JK^H (K < J <= I); wave 0 first updates
+        // the next diagonal block and factors it (look-ahead)
+        const int m = NB - K - 1, nt = m * (m + 1) / 2;
+        if (wave == 0) {
+            if (m > 0) {
+                const int b1 = cb_bidx(K + 1, K + 1), bk = cb_bidx(K + 1, K);
+                cb_sub_abh_mfma(s_re + 256 * bk, s_im + 256 * bk, s_re + 256 * bk, s_im + 256 * bk,
+                                s_re + 256 * b1, s_im + 256 * b1, lane);
+                cb_wave_sync();
+                cb_chol_diag(s_re + 256 * b1, s_im + 256 * b1, dall + CB * (K + 1), csw, lane, bad);
+            }
+        } else {
+            for (int t = wave - 1; t < nt; t += CB_WAVES - 1) {
+                int ii = 0;
+                while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+                const int jj = t - ii * (ii + 1) / 2;
+                if (ii == 0 && jj == 0) continue;   // the next diagonal block (wave 0)
+                const int I = K + 1 + ii, J = K + 1 + jj;
+                const int bi_ = cb_bidx(I, K), bj = cb_bidx(J, K), bo = cb_bidx(I, J);
+                cb_sub_abh_mfma(s_re + 256 * bi_, s_im + 256 * bi_, s_re + 256 * bj, s_im + 256 * bj,
+                                s_re + 256 * bo, s_im + 256 * bo, lane);
+            }
+        }
+        __syncthreads();
+    }
+    if (bad && lane == 0) atomicOr(&s_bad, 1);
+    // inverses of the diagonal blocks, one wave each
+    if (wave < NB)
+        cb_inv_diag(s_re + 256 * cb_bidx(wave, wave), s_im + 256 * cb_bidx(wave, wave), dall + CB * wave,
+                    Xr + CB * wave + (int64_t)Dp * CB * wave, Xi + CB * wave + (int64_t)Dp * CB * wave, Dp, csw, lane);
+    // R = L^H (upper): R[k, a] = conj(L[a, k])
+    for (int a = wave; a < D; a += CB_WAVES)
+        for (int k = lane; k < D; k += 64) {
+            double vr = 0.0, vi = 0.0;
+            if (a >= k) {
+                const int q = 256 * cb_bidx(a >> 4, k >> 4) + (a & 15) + CB * (k & 15);
+                vr = s_re[q];
+                vi = -s_im[q];
+            }
+            R[k + (int64_t)D * a] = vr;
+            R[DD + k + (int64_t)D * a] = vi;
+        }
+    __threadfence_block();
+    __syncthreads();
+    // inverse by block diagonals: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ; the
+    // diagonal slots of L are free now and hold each wave's intermediate T
+    for (int dl = 1; dl < NB; ++dl) {
+        const int J = wave, I = J + dl;
+        if (I < NB) {
+            const int m = lane & 15, q = lane >> 4;
+            // B fragments X_KJ[kk + q][m] of every K of this level, then A = L_IK
+            double xb_r[4 * (CB_MAXNB - 1)], xb_i[4 * (CB_MAXNB - 1)];
+#pragma unroll
+            for (int t = 0; t < CB_MAXNB - 1; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int K = J + t;
+                    const bool ok = t < dl;
+                    const int64_t g = ok ? (CB * K + 4 * j + q) + (int64_t)Dp * (CB * J + m) : 0;
+                    xb_r[4 * t + j] = ok ? Xr[g] : 0.0;
+                    xb_i[4 * t + j] = ok ? Xi[g] : 0.0;
+                }
+            double xa_r[4], xa_i[4];   // A fragments of X_II[m][kk + q]
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t g = (CB * I + m) + (int64_t)Dp * (CB * I + 4 * j + q);
+                xa_r[j] = Xr[g];
+                xa_i[j] = Xi[g];
+            }
+            cb_d4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < CB_MAXNB - 1; ++t) {
+                if (t < dl) {
+                    const double* Lr = s_re + 256 * cb_bidx(I, J + t);
+                    const double* Li = s_im + 256 * cb_bidx(I, J + t);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int ia = m + CB * (4 * j + q);
+                        const double lr = Lr[ia], li = Li[ia], br = xb_r[4 * t + j], bi = xb_i[4 * t + j];
+                        tr = cb_mfma(lr, br, tr);
+                        tr = cb_mfma(-li, bi, tr);
+                        ti = cb_mfma(lr, bi, ti);
+                        ti = cb_mfma(li, br, ti);
+                    }
+                }
+            }
+            // X_IJ = - X_II T: the output layout of T is the B fragment layout
+            cb_d4 orr = {0, 0, 0, 0}, oi = {0, 0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                orr = cb_mfma(-xa_r[j], tr[j], orr);
+                orr = cb_mfma(xa_i[j], ti[j], orr);
+                oi = cb_mfma(-xa_r[j], ti[j], oi);
+                oi = cb_mfma(-xa_i[j], tr[j], oi);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t g = (CB * I + q + 4 * r) + (int64_t)Dp * (CB * J + m);
+                Xr[g] = orr[r];
+                Xi[g] = oi[r];
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    for (int j = wave; j < D; j += CB_WAVES)
+        for (int i = lane; i < D; i += 64) {
+            const bool lo = i >= j;
+            const int64_t g = i + (int64_t)Dp * j;
+            Linv[i + (int64_t)D * j] = lo ? Xr[g] : 0.0;
+            Linv[DD + i + (int64_t)D * j] = lo ? Xi[g] : 0.0;
+        }
+    __syncthreads();
+    if (tid == 0 && s_bad) atomicExch(&st->bad, 1);
+}
+
+}  // namespace
+
 void chol_inv(const double* G, int D, double* Linv, double* R, const double* Rprev, double* work,
               StepDev* st, hipStream_t s) {
     if (g_dry_run) return;
-    if (D <= CHOL_LDS_MAX)
-        hipLaunchKernelGGL((k_chol_inv<true, 2, 16>), dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R, Rprev,
-                           work, st);
+    if (D <= CB * CB_MAXNB && !Rprev)
+        hipLaunchKernelGGL(k_chol_blk, dim3(1), dim3(CB_THREADS), 0, s, G, D, Linv, R, work, st);
     else
         hipLaunchKernelGGL((k_chol_inv<false, 4, 8>), dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R, Rprev,
                            work, st);

@@ -110,7 +110,9 @@ void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s);
 
 // Cholesky of a Hermitian D x D Gram matrix G (planar, column-major):
 // G = L L^H.  Writes Linv (lower, L^{-1}) and R = L^H (upper), or R = L^H * Rprev
-// when Rprev != nullptr.  Sets st->bad on a non-positive pivot.
+// when Rprev != nullptr (D > 128 only).  Sets st->bad on a non-positive pivot.
+// work: 2 Dp^2 doubles (Dp = 16 ceil(D / 16)) for D <= 128, else
+// D (D + 1) + 32 D.
 void chol_inv(const double* G, int D, double* Linv, double* R, const double* Rprev, double* work,
               StepDev* st, hipStream_t s);
 
