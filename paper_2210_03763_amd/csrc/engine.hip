@@ -718,6 +718,13 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
         stage_f32(h, o, nullptr);
     }
     lz_start(x, n, h->Vk, lz, h->red, nb, s);
+    if (n <= LZ_SMALL_N) {
+        for (int j = 0; j < h->m; ++j) {
+            apply_op_prec(h, o, h->Vk + 2 * n * j, h->W, &lz->done);
+            lz_iter_small(h->Vk, j, h->m, h->W, n, lz, LANCZOS_TOL, s);
+        }
+        return;
+    }
     for (int j = 0; j < h->m; ++j) {
         double* vj = h->Vk + 2 * n * j;
         apply_op_prec(h, o, vj, h->W, &lz->done);

@@ -33,6 +33,35 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;   // valid in thread 0
 }
 
+// Sums 32 values over the block with one barrier: a butterfly inside each
+// wave leaves value ((l>>5)&1)*16 + ((l>>4)&1)*8 + ((l>>3)&1)*4 + ((l>>2)&1)*2
+// + ((l>>1)&1) in lane l, the waves' results meet in sh (32 per wave).
+// Returns the block total of value threadIdx.x in threads 0..31.
+__device__ inline double block_sum32(double (&a)[32], double* sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int h = 16; h >= 1; h >>= 1) {
+        const int mask = 2 * h;   // lane bit separating the halves of this step
+        const bool hi = (lane & mask) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const double send = hi ? a[i] : a[i + h];
+            const double keep = hi ? a[i + h] : a[i];
+            a[i] = keep + __shfl_xor(send, mask, 64);
+        }
+    }
+    a[0] += __shfl_xor(a[0], 1, 64);
+    const int idx = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
+                    ((lane >> 1) & 1);
+    __syncthreads();
+    if ((lane & 1) == 0) sh[32 * wv + idx] = a[0];
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x < 32)
+        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) r += sh[32 * w2 + threadIdx.x];
+    return r;
+}
+
 __global__ void k_norm2_partial(const double* x, int64_t n, double* partial, const int* skip) {
     if (skip && *skip) return;
     __shared__ double sh[16];
@@ -79,10 +108,10 @@ __global__ void k_scale_by(const double* x, int64_t n, double* y, const LanczosD
 }
 
 // partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < kcount
-__global__ void k_multidot_partial(const double* V, int kcount, const double* w, int64_t n,
-                                   double* partial, const LanczosDev* lz) {
+__global__ __launch_bounds__(256) void k_multidot_partial(const double* V, int kcount, const double* w, int64_t n,
+                                                         double* partial, const LanczosDev* lz) {
     if (lz->done) return;
-    __shared__ double sh[16];
+    __shared__ double sh32[4 * 32];
     double re[KRYLOV_MAX], im[KRYLOV_MAX];
     for (int k = 0; k < KRYLOV_MAX; ++k) re[k] = im[k] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -104,12 +133,14 @@ __global__ void k_multidot_partial(const double* V, int kcount, const double* w,
             }
         }
     }
-    for (int k = 0; k < kcount; ++k) {
-        const double a = block_sum(re[k], sh);
-        if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2] = a;
-        const double b = block_sum(im[k], sh);
-        if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2 + 1] = b;
+    double a[32];
+#pragma unroll
+    for (int k = 0; k < KRYLOV_MAX; ++k) {
+        a[2 * k] = re[k];
+        a[2 * k + 1] = im[k];
     }
+    const double t = block_sum32(a, sh32);
+    if (threadIdx.x < 2 * kcount) partial[blockIdx.x * KRYLOV_MAX * 2 + threadIdx.x] = t;
 }
 
 __global__ void k_multidot_final(const double* partial, int nb, int kcount, LanczosDev* lz,
@@ -145,6 +176,7 @@ __global__ __launch_bounds__(256) void k_sub_fused(const double* V, int kcount, 
     if (lz->done) return;
     __shared__ double c[2 * KRYLOV_MAX];
     __shared__ double sh[16];
+    __shared__ double sh32[4 * 32];
     if (threadIdx.x < 2 * KRYLOV_MAX) c[threadIdx.x] = lz->c[threadIdx.x];
     __syncthreads();
     double pr[KRYLOV_MAX], pi[KRYLOV_MAX], nrm = 0;
@@ -184,15 +216,115 @@ __global__ __launch_bounds__(256) void k_sub_fused(const double* V, int kcount, 
         }
     }
     if (MODE == 1) {
-        for (int k = 0; k < kcount; ++k) {
-            const double a = block_sum(pr[k], sh);
-            if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2] = a;
-            const double b2 = block_sum(pi[k], sh);
-            if (threadIdx.x == 0) partial[(blockIdx.x * KRYLOV_MAX + k) * 2 + 1] = b2;
+        double a[32];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k) {
+            a[2 * k] = pr[k];
+            a[2 * k + 1] = pi[k];
         }
+        const double t = block_sum32(a, sh32);
+        if (threadIdx.x < 2 * kcount) partial[blockIdx.x * KRYLOV_MAX * 2 + threadIdx.x] = t;
     } else if (MODE == 2) {
         const double a = block_sum(nrm, sh);
         if (threadIdx.x == 0) partial[blockIdx.x] = a;
+    }
+}
+
+// One whole Lanczos iteration after the matvec for short vectors (one block):
+// c = V^H w (alpha_j = Re c_j); unless j is the last index: w -= V c,
+// c' = V^H w, w -= V c', beta_j = |w| with the breakdown test, v_{j+1} = w / beta_j.
+__global__ __launch_bounds__(256) void k_lz_iter_small(double* V, int j, int m, double* w, int64_t n, LanczosDev* lz,
+                                                       double tol) {
+    if (lz->done) return;
+    __shared__ double sh32[4 * 32];
+    __shared__ double c[32];
+    __shared__ double s_beta;
+    __shared__ int s_stop;
+    const int kc = j + 1;
+    double a[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a[k] = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double wr = w[i], wi = w[i + n];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k)
+            if (k < kc) {
+                const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
+                a[2 * k] += vr * wr + vi * wi;
+                a[2 * k + 1] += vr * wi - vi * wr;
+            }
+    }
+    double t = block_sum32(a, sh32);
+    if (threadIdx.x < 32) c[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        lz->alpha[j] = c[2 * j];
+        lz->m_eff = j + 1;
+    }
+    if (j == m - 1) return;
+    // subtract, second projection
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a[k] = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double wr = w[i], wi = w[i + n];
+        double vr[KRYLOV_MAX], vi[KRYLOV_MAX];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k)
+            if (k < kc) {
+                vr[k] = V[2 * n * k + i];
+                vi[k] = V[2 * n * k + n + i];
+                wr -= c[2 * k] * vr[k] - c[2 * k + 1] * vi[k];
+                wi -= c[2 * k] * vi[k] + c[2 * k + 1] * vr[k];
+            }
+        w[i] = wr;
+        w[i + n] = wi;
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k)
+            if (k < kc) {
+                a[2 * k] += vr[k] * wr + vi[k] * wi;
+                a[2 * k + 1] += vr[k] * wi - vi[k] * wr;
+            }
+    }
+    t = block_sum32(a, sh32);
+    __syncthreads();
+    if (threadIdx.x < 32) c[threadIdx.x] = t;
+    __syncthreads();
+    // subtract again, norm
+    double nrm[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) nrm[k] = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double wr = w[i], wi = w[i + n];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k)
+            if (k < kc) {
+                const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
+                wr -= c[2 * k] * vr - c[2 * k + 1] * vi;
+                wi -= c[2 * k] * vi + c[2 * k + 1] * vr;
+            }
+        w[i] = wr;
+        w[i + n] = wi;
+        nrm[0] += wr * wr + wi * wi;
+    }
+    t = block_sum32(nrm, sh32);
+    if (threadIdx.x == 0) {
+        const double b = sqrt(t);
+        const double bprev = j > 0 ? lz->beta[j - 1] : 0.0;
+        const bool stop = !(b > tol * (fabs(lz->alpha[j]) + bprev));
+        if (stop)
+            lz->done = 1;
+        else
+            lz->beta[j] = b;
+        s_stop = stop;
+        s_beta = b;
+    }
+    __syncthreads();
+    if (s_stop) return;
+    const double inv = 1.0 / s_beta;
+    double* vn = V + 2 * n * (j + 1);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        vn[i] = w[i] * inv;
+        vn[i + n] = w[i + n] * inv;
     }
 }
 
@@ -370,6 +502,11 @@ void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double*
     hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, w, n, partial, &lz->done);
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s, partial, nb, lz, j, tol);
     hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j);
+}
+
+void lz_iter_small(double* V, int j, int m, double* w, int64_t n, LanczosDev* lz, double tol, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_lz_iter_small, dim3(1), dim3(256), 0, s, V, j, m, w, n, lz, tol);
 }
 
 void lz_expm(LanczosDev* lz, double tau, StepDev* st, hipStream_t s) {

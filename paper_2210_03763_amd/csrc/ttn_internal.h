@@ -96,6 +96,10 @@ void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double*
                       double* partial, int nb, double tol, hipStream_t s);
 void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
              double tol, hipStream_t s);
+// a whole iteration after the matvec (projection, two Gram-Schmidt passes,
+// beta_j and breakdown, v_{j+1}) in one block, for n <= LZ_SMALL_N
+constexpr int64_t LZ_SMALL_N = 1024;
+void lz_iter_small(double* V, int j, int m, double* w, int64_t n, LanczosDev* lz, double tol, hipStream_t s);
 void lz_expm(LanczosDev* lz, double tau, StepDev* st, hipStream_t s);
 void lz_combine(const double* V, int64_t n, double* out, LanczosDev* lz, hipStream_t s);
 
