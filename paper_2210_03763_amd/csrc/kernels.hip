@@ -37,19 +37,25 @@ __device__ inline double block_sum(double v, double* sh) {
 // wave leaves value ((l>>5)&1)*16 + ((l>>4)&1)*8 + ((l>>3)&1)*4 + ((l>>2)&1)*2
 // + ((l>>1)&1) in lane l, the waves' results meet in sh (32 per wave).
 // Returns the block total of value threadIdx.x in threads 0..31.
+template <int H>
+__device__ inline void butterfly_step(double (&a)[32], int lane) {
+    // lanes that differ in bit 2H exchange one half of their first 2H values
+    const bool hi = (lane & (2 * H)) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double send = hi ? a[i] : a[i + H];
+        const double keep = hi ? a[i + H] : a[i];
+        a[i] = keep + __shfl_xor(send, 2 * H, 64);
+    }
+}
+
 __device__ inline double block_sum32(double (&a)[32], double* sh) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int h = 16; h >= 1; h >>= 1) {
-        const int mask = 2 * h;   // lane bit separating the halves of this step
-        const bool hi = (lane & mask) != 0;
-#pragma unroll
-        for (int i = 0; i < h; ++i) {
-            const double send = hi ? a[i] : a[i + h];
-            const double keep = hi ? a[i + h] : a[i];
-            a[i] = keep + __shfl_xor(send, mask, 64);
-        }
-    }
+    butterfly_step<16>(a, lane);
+    butterfly_step<8>(a, lane);
+    butterfly_step<4>(a, lane);
+    butterfly_step<2>(a, lane);
+    butterfly_step<1>(a, lane);
     a[0] += __shfl_xor(a[0], 1, 64);
     const int idx = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
                     ((lane >> 1) & 1);
