@@ -68,3 +68,25 @@ def test_8x8_d4_chi128_mixed_vs_fp64_and_invariants():
     assert np.abs(p1[idle] - p0[idle]).max() <= 1e-8, res
     g64.close()
     gm.close()
+
+
+def test_8x8_d4_chi256_repetition_code_mixed_vs_fp64():
+    # the chi = 256 network (256^3 nodes, Cholesky of 256 x 256 Gram matrices
+    # outside LDS): one step of the repetition-code program, mixed against FP64
+    w = W.config("c5")
+    n = 1
+    _say("[large] c5 fp64 1 step")
+    g64 = T.TTN(w.copy(precision=T.PREC_FP64))
+    s64 = g64.step(n, stats=True)
+    F64, _ = g64.fidelity()
+    _say("[large] c5 mixed 1 step")
+    gm = T.TTN(w)
+    sm = gm.step(n, stats=True)
+    Fm, _ = gm.fidelity()
+    C = 1 - abs(gm.overlap(g64)) ** 2
+    res = dict(C=C, dF=abs(Fm - F64), n64=s64[-1]["norm2"], nm=sm[-1]["norm2"], F=F64)
+    _say(f"[large] {res}")
+    assert C <= 1e-5 and abs(Fm - F64) <= 1e-5, res
+    assert abs(s64[-1]["norm2"] - 1) <= 1e-10 and abs(sm[-1]["norm2"] - 1) <= 1e-6, res
+    g64.close()
+    gm.close()
