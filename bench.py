@@ -204,6 +204,45 @@ def run_adjoint(w, steps):
             "max_abs_grad": float(max(abs(go).max(), abs(gd).max()))}
 
 
+def sample_flops_per_shot(w) -> float:
+    """Algorithmic real flops of one shot: at every node above the bottom the
+    batch GEMMs B = Q u and phi = Q^T (phi_L (x) phi_R), 8 D_L D_R D_P each."""
+    N, d, chi = w.n_sites, w.d, w.chi
+    K = int(round(math.log2(N)))
+
+    def link(s):
+        return 1 if s >= N else min(chi, d ** min(s, 64), d ** min(N - s, 64))
+
+    total = 0.0
+    for lvl in range(1, K):
+        nn = N >> (lvl + 1)
+        dc, dp = link(1 << lvl), link(1 << (lvl + 1))
+        total += nn * 2 * 8.0 * dc * dc * dp
+    return total
+
+
+def run_sampling(w, shots, warm_steps=2):
+    import torch
+    from paper_2210_03763_amd import ttn
+    g = ttn.TTN(w.copy(precision=ttn.PREC_FP64), device="cuda:0")
+    g.step(warm_steps)
+    g.sample(1000, 1)           # first-use costs outside the timing
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cfg, amp = g.sample(shots, 2210037635)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    g.close()
+    fl = sample_flops_per_shot(w) * shots
+    import numpy as np
+    _, first = np.unique(cfg, axis=0, return_index=True)
+    return {"shots": shots, "seconds": round(el, 3), "shots_per_s": round(shots / el, 1),
+            "gemm_tflop": round(fl / 1e12, 2), "gemm_tflops_over_the_call": round(fl / el / 1e12, 2),
+            "fp64_mfma_peak": PEAK_TFLOPS["fp64"], "state": f"FP64 network after {warm_steps} steps",
+            "distinct_configs": int(len(first)),
+            "probability_covered": float((abs(amp[first]) ** 2).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +254,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--adjoint-steps", type=int, default=2,
                     help="recorded steps of the forward+adjoint measurement (0: skip)")
+    ap.add_argument("--sample-shots", type=int, default=1000000,
+                    help="projective-measurement shots of the sampling measurement (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -282,6 +323,9 @@ def main():
                 max(1e-9, adj["mixed"]["fwd_ms_per_step"] + adj["mixed"]["bwd_ms_per_step"])
             adj["mixed_speedup_fwd_adj"] = round(adj["mixed_speedup_fwd_adj"], 3)
         out["forward_adjoint"] = adj
+    if args.sample_shots > 0:
+        print(f"[bench] sampling: {args.sample_shots} shots", file=sys.stderr, flush=True)
+        out["sampling"] = run_sampling(w, args.sample_shots)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w.copy(precision=0), fps, args.cpu_budget)

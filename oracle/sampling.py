@@ -134,7 +134,7 @@ def sample(st: OracleTTN, n_shots: int, seed: int, shot0: int = 0):
 
 def config_amplitude(st: OracleTTN, config) -> complex:
     """<s|psi> for one configuration, by the network's product-state overlap."""
-    d = st.d
+    d = st.tree.d
     states = np.zeros((st.tree.N, d), dtype=np.complex128)
     for s, x in enumerate(config):
         states[s, int(x)] = 1.0

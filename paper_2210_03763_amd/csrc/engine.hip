@@ -1442,6 +1442,7 @@ void check_step_flags(ttn_handle* h, StepDev* out) {
 }
 
 #include "adjoint.inc"
+#include "sampling.inc"
 
 // A device-free handle for plan checks: workspace carved at a fake address,
 // the initial network built and a one-segment program with a gate on every site.
@@ -1872,6 +1873,13 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         std::vector<double> go((size_t)N * h->n_seg), gd((size_t)N * h->n_seg);
         rc = ttn_backward(h, N, all.data(), 1.0, go.data(), gd.data());
         if (rc != TTN_OK) throw StatusError{rc, h->err};
+        size_t sbytes = 0;
+        rc = ttn_sample_query(h, 3, &sbytes);
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        std::vector<uint8_t> cfgs(7 * (size_t)N);
+        std::vector<double> amp(14);
+        rc = ttn_sample(h, 7, 1, 0, (void*)(uintptr_t(1) << 47), sbytes, cfgs.data(), amp.data());
+        if (rc != TTN_OK) throw StatusError{rc, h->err};
         g_dry_run = false;
         report("ok");
         ttn_destroy(h);
@@ -1886,6 +1894,28 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         report("unexpected exception");
         if (h) ttn_destroy(h);
         return TTN_EINVAL;
+    }
+}
+
+int ttn_sample_query(ttn_handle* h, int32_t batch, size_t* device_bytes) {
+    if (!h || !device_bytes || batch < 1) return TTN_EINVAL;
+    SampleBufs probe;
+    *device_bytes = sample_carve(h, batch, nullptr, 0, &probe) + 256;
+    return TTN_OK;
+}
+
+int ttn_sample(ttn_handle* h, int64_t n_shots, uint64_t seed, int64_t shot0, void* d_buf, size_t bytes,
+               uint8_t* configs, double* amps) {
+    if (!h) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (n_shots < 0 || shot0 < 0 || !d_buf) throw StatusError{TTN_EINVAL, "bad shot count or buffer"};
+        if (h->d > 8) throw StatusError{TTN_ENOTSUP, "sampling supports d <= 8"};
+        sample_shots(h, n_shots, seed, shot0, (char*)d_buf, bytes, configs, amps);
+        if (!h->dry) HIPCHECK(hipGetLastError());
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
     }
 }
 

@@ -70,6 +70,8 @@ def lib():
             "ttn_overlap": (C.c_int, [P, P, DP]),
             "ttn_export_state": (I64, [P, DP, I64]),
             "ttn_set_graphs": (C.c_int, [P, I32]),
+            "ttn_sample_query": (C.c_int, [P, I32, C.POINTER(C.c_size_t)]),
+            "ttn_sample": (C.c_int, [P, I64, C.c_uint64, I64, P, C.c_size_t, C.POINTER(C.c_uint8), DP]),
             "ttn_adjoint_query": (C.c_int, [C.POINTER(Config), I32, I32, C.POINTER(C.c_size_t)]),
             "ttn_record_begin": (C.c_int, [P, I32, I32, P, C.c_size_t]),
             "ttn_backward": (C.c_int, [P, I32, IP, D, DP, DP]),
@@ -229,6 +231,20 @@ class TTN:
         rc = lib().ttn_backward(self.h, len(ts), _iptr(ts), float(dF), _dptr(go), _dptr(gd))
         self._check(rc, self.h)
         return go, gd
+
+    def sample(self, n_shots: int, seed: int, shot0: int = 0, batch: int = 8192):
+        """n_shots projective measurements of all sites: (configs [n][N] uint8,
+        amplitudes psi(s) [n] complex)."""
+        import torch
+        nbytes = C.c_size_t(0)
+        self._check(lib().ttn_sample_query(self.h, int(max(1, min(batch, n_shots))), C.byref(nbytes)), self.h)
+        buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        cfg = np.zeros((n_shots, self.w.n_sites), dtype=np.uint8)
+        amp = np.zeros(2 * n_shots)
+        rc = lib().ttn_sample(self.h, int(n_shots), C.c_uint64(seed), int(shot0), C.c_void_p(buf.data_ptr()), nbytes,
+                              cfg.ctypes.data_as(C.POINTER(C.c_uint8)), _dptr(amp))
+        self._check(rc, self.h)
+        return cfg, amp.view(np.complex128)
 
     def export_state(self) -> np.ndarray:
         n = lib().ttn_export_state(self.h, None, 0)
