@@ -174,6 +174,27 @@ int ttn_record_begin(ttn_handle* h, int32_t n_steps, int32_t ckpt_every, void* d
 int ttn_backward(ttn_handle* h, int32_t n_target, const int32_t* target_sites, double dF, double* grad_omega,
                  double* grad_delta);
 
+/* Projective measurements of all sites (Sec. on parallel quantum algorithms:
+ * the paper's measurement histograms come from a million shots drawn from
+ * the TTN).  Each shot is drawn exactly from |psi(s)|^2 of the current
+ * (root-canonical) state, top-down through the tree: a node's pure input
+ * state u on its parent link gives B = Q u on its child links, the left
+ * subtree is sampled from one column of B picked with the weights
+ * ||B[:, r]||^2, the right subtree from its exact conditional state, bottom
+ * nodes draw their two sites in turn.  Uniforms come from Philox4x32-10
+ * with counter (shot low word, shot high word, draw index, 0) and key
+ * (seed low word, seed high word); node v uses draw v, bottom node j draws
+ * n_nodes + 2 j and n_nodes + 2 j + 1 (shot0 + b is the shot index of shot b,
+ * so a run can be split over calls).
+ *   configs: host [n_shots][N] (site-indexed values 0..d-1) or NULL;
+ *   amps: host [n_shots] complex psi(s) of each drawn configuration, or NULL.
+ * d_buf: caller-owned device scratch; shots are processed in batches as
+ * large as it allows (ttn_sample_query gives the bytes for a batch size).
+ * The state is not changed. */
+int ttn_sample_query(ttn_handle* h, int32_t batch, size_t* device_bytes);
+int ttn_sample(ttn_handle* h, int64_t n_shots, uint64_t seed, int64_t shot0, void* d_buf, size_t bytes,
+               uint8_t* configs, double* amps);
+
 /* The tensor-product-operator contraction on one leg of node tensors
  * (Sec. "Tensor network simulations": each term of the Hamiltonian acts on
  * a node through its environment operators), on caller device memory:
@@ -226,7 +247,8 @@ int ttn_set_graphs(ttn_handle* h, int32_t enabled);
 /* Checks the launch plan of a configuration without a device: walks
  * initialisation, n_steps TDVP steps of a one-segment program with a gate on
  * every site (recorded for the adjoint), the fidelity, a local expectation,
- * a self overlap and the backward pass, and verifies that every kernel
+ * a self overlap, the backward pass and a few sampled shots, and verifies
+ * that every kernel
  * operand stays inside its workspace or adjoint-buffer allocation.
  * No device memory is touched.  msg (may be NULL) receives "ok" or the first
  * violation.  Not thread safe with concurrent device calls of this library. */
