@@ -29,7 +29,12 @@ What it computes (paper sections in brackets):
     exponentials by Lanczos with full re-orthogonalisation; the small
     tridiagonal exponential through its symmetric eigendecomposition.
   * Observables: GHZ fidelity F = |<GHZ|psi>|^2 [Sec. on GHZ results],
-    norm [open-system section], state overlap for C(p1, p2) [Tab. conv8x8].
+    norm [open-system section], state overlap for C(p1, p2) [Tab. conv8x8],
+    the total Rydberg population sum_i <n_i> [definitions of P_R and T_R].
+  * Open system [Eq. (eq:hoqs)]: with a decay rate gamma > 0 every site's
+    local term gains -i gamma |r><r|; the state is then not normalised
+    (its norm is the no-decay probability), and the local exponentials use
+    Arnoldi with a dense Hessenberg exponential instead of Lanczos.
   * Gradient of F with respect to the pulse table (the paper optimises
     pulses but gives no gradient method): the exact derivative of this
     discrete map, by reverse-mode automatic differentiation through every
@@ -201,6 +206,52 @@ def lanczos_expm(apply, v0, tau: float, m: int):
     return out, dict(m=k, beta=[float(b.detach()) for b in betas])
 
 
+def arnoldi_expm(apply, v0, tau: float, m: int):
+    """exp(-i tau H) v0 in the Krylov space of dimension <= m for a general
+    (non-Hermitian) H, as needed by the open-system Hamiltonian.
+
+    Arnoldi: each new vector H v_j is orthogonalised against all previous
+    basis vectors by two classical Gram-Schmidt passes, and the projection
+    coefficients of both passes make up column j of the upper Hessenberg
+    matrix H_m (the last column takes the first pass only, since no further
+    basis vector is formed); h_{j+1,j} = ||w||, happy breakdown when
+    h_{j+1,j} <= tol (|Re h_jj| + h_{j,j-1}) with the first-pass h_jj.  The
+    small exponential exp(-i tau H_m) e_1 comes from the dense matrix
+    exponential."""
+    beta0 = torch.linalg.vector_norm(v0)
+    if float(beta0.detach()) == 0.0:
+        return v0.clone(), dict(m=0, beta=[])
+    V = [v0 / beta0]
+    Hm = torch.zeros(m + 1, m, dtype=CDT)
+    k = 0
+    for j in range(m):
+        w = apply(V[j])
+        coef = [torch.vdot(Vk.reshape(-1), w.reshape(-1)) for Vk in V]
+        first_diag = coef[j]
+        for i, ck in enumerate(coef):
+            Hm[i, j] = Hm[i, j] + ck
+        k = j + 1
+        if j == m - 1:
+            break
+        for ck, Vk in zip(coef, V):
+            w = w - ck * Vk
+        coef = [torch.vdot(Vk.reshape(-1), w.reshape(-1)) for Vk in V]
+        for i, (ck, Vk) in enumerate(zip(coef, V)):
+            w = w - ck * Vk
+            Hm[i, j] = Hm[i, j] + ck
+        b = torch.linalg.vector_norm(w)
+        bprev = float(Hm[j, j - 1].real) if j > 0 else 0.0
+        if float(b) <= LANCZOS_BREAKDOWN * (abs(float(first_diag.real)) + bprev):
+            break
+        Hm[j + 1, j] = b
+        V.append(w / b)
+    y = torch.linalg.matrix_exp(-1j * tau * Hm[:k, :k])[:, 0]
+    out = torch.zeros_like(v0)
+    for i in range(k):
+        out = out + (beta0 * y[i]) * V[i]
+    return out, dict(m=k, beta=[float(Hm[i + 1, i].real) for i in range(k - 1)])
+
+
 # ---------------------------------------------------------------------------
 # tree
 # ---------------------------------------------------------------------------
@@ -286,10 +337,11 @@ class Tree:
 
 class OracleTTN:
     def __init__(self, n_sites, d, chi, pos_xy, leaf_order, c6=1.0, r_cut=0.0, leak_ratio=0.0,
-                 krylov_dim=12):
+                 krylov_dim=12, gamma=0.0):
         self.tree = Tree(n_sites, d, chi, leaf_order)
         self.d = d
         self.m = krylov_dim
+        self.gamma = float(gamma)
         self.V = vdw_matrix(torch.as_tensor(pos_xy, dtype=RDT), c6, r_cut)
         self.X, self.n, self.Lk = local_ops(d)
         self.leak_ratio = leak_ratio
@@ -364,7 +416,11 @@ class OracleTTN:
     def h_local(self, site):
         om = self.omega_t[site]
         de = self.delta_t[site]
-        return (om / 2) * (self.X + self.leak_ratio * self.Lk) - de * self.n
+        h = (om / 2) * (self.X + self.leak_ratio * self.Lk) - de * self.n
+        if self.gamma != 0.0:
+            # open system: decay out of |r> as the non-Hermitian term -i gamma |r><r|
+            h = h - 1j * self.gamma * self.n
+        return h
 
     # -- environments ----------------------------------------------------
     def child_env(self, v, side):
@@ -471,13 +527,18 @@ class OracleTTN:
             return out
         return apply
 
+    def _expm(self, apply, x, tau):
+        if self.gamma != 0.0:
+            return arnoldi_expm(apply, x, tau, self.m)
+        return lanczos_expm(apply, x, tau, self.m)
+
     def evolve_node(self, v, tau):
-        out, info = lanczos_expm(self.heff(v), self.T[v], tau, self.m)
+        out, info = self._expm(self.heff(v), self.T[v], tau)
         self.T[v] = out
         self.stats.append(("node", v, info["m"]))
 
     def evolve_bond(self, v, C, tau):
-        out, info = lanczos_expm(self.keff(v), C, -tau, self.m)
+        out, info = self._expm(self.keff(v), C, -tau)
         self.stats.append(("bond", v, info["m"]))
         return out
 
@@ -537,8 +598,14 @@ class OracleTTN:
     def norm2(self):
         return float(torch.linalg.vector_norm(self.T[self.tree.root]) ** 2)
 
+    def rydberg_population(self):
+        """sum_i <psi|n_i|psi> (unnormalised state): the total |r> population,
+        whose time integral is the integrated time in the Rydberg state."""
+        return sum(self.local_expectation(s, self.n).real for s in range(self.tree.N))
+
     def energy(self):
-        """<psi|H|psi> with the centre at the root and current environments."""
+        """Re <psi|H|psi> with the centre at the root and current environments
+        (the real part is the whole value for a Hermitian H)."""
         r = self.tree.root
         T = self.T[r]
         return float(torch.vdot(T.reshape(-1), self.heff(r)(T).reshape(-1)).real)
@@ -628,7 +695,7 @@ def ttn_overlap(A: OracleTTN, B: OracleTTN) -> complex:
 def build(w) -> OracleTTN:
     """Oracle state from a workload description (attribute access only)."""
     st = OracleTTN(w.n_sites, w.d, w.chi, w.pos_xy, w.leaf_order, w.c6, w.r_cut, w.leak_ratio,
-                   w.krylov_dim)
+                   w.krylov_dim, getattr(w, "gamma", 0.0))
     st.init_product(w.init_product, w.dress_eps, w.dress_noise)
     return st
 
@@ -656,7 +723,10 @@ def run(w, n_steps: Optional[int] = None, st: Optional[OracleTTN] = None, step0:
         st.sweep_fwd(tau)
         st.sweep_bwd(tau)
         if record:
-            recs.append(dict(step=n, norm2=st.norm2(), energy=st.energy()))
+            rec = dict(step=n, norm2=st.norm2(), energy=st.energy())
+            if st.gamma != 0.0:
+                rec["rydberg_population"] = st.rydberg_population()
+            recs.append(rec)
     if apply_final_events:
         end = step0 + n_steps
         for (k, s, U) in w.events:

@@ -69,6 +69,7 @@ class Workload:
     target_sites: np.ndarray  # sites that carry the GHZ-type target; others are |0>
     seed: int
     ckpt_every: int = 0
+    gamma: float = 0.0        # Rydberg decay rate of the open-system mode (0: closed system)
 
     @property
     def n_sites(self) -> int:
