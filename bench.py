@@ -144,7 +144,7 @@ def calibration_copy(mib):
           flush=True)
 
 
-def run_gpu(w, steps, warmup, profile=True, calib_mib=0):
+def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True):
     """Warm-up steps (the first captures the step graph), `steps` timed steps
     replayed from the graph, then -- with profile -- `steps` more steps in a
     profiling window (launched eagerly, each contraction bracketed by HIP
@@ -155,13 +155,17 @@ def run_gpu(w, steps, warmup, profile=True, calib_mib=0):
     L.ttn_profile_begin.argtypes = [C.c_void_p]
     L.ttn_profile_end.argtypes = [C.c_void_p, C.POINTER(Profile)]
     g = ttn.TTN(w, device="cuda:0")
+    if not graphs:
+        g.set_graphs(False)
     if warmup:
         g.step(warmup)
     torch.cuda.synchronize()
+    print(f"[bench] {warmup} warm-up step(s) done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     g.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print(f"[bench] {steps} timed step(s) done", file=sys.stderr, flush=True)
     prof = Profile()
     ms_prof = None
     if profile:
@@ -174,6 +178,7 @@ def run_gpu(w, steps, warmup, profile=True, calib_mib=0):
         t3 = time.perf_counter()
         assert L.ttn_profile_end(g.h, C.byref(prof)) == 0
         ms_prof = (t3 - t2) * 1e3 / steps
+        print(f"[bench] {steps} profiled step(s) done", file=sys.stderr, flush=True)
     F, _ = g.fidelity()
     n2, E = g.observables()
     return g, (t1 - t0) * 1e3 / steps, prof, ms_prof, F, n2, E
@@ -202,6 +207,32 @@ def run_adjoint(w, steps):
     return {"steps": steps, "fwd_ms_per_step": round(1e3 * fwd, 2), "bwd_ms_per_step": round(1e3 * bwd, 2),
             "fwd_adj_steps_per_s": round(1.0 / (fwd + bwd), 4), "adjoint_buffer_gib": round(nbytes / 2 ** 30, 2),
             "max_abs_grad": float(max(abs(go).max(), abs(gd).max()))}
+
+
+def run_open(w, steps, warmup, gamma):
+    """Open-system mode (Eq. (eq:hoqs): -i gamma |r><r| per site, Arnoldi
+    local exponentials) on the same workload: timed steps from the step
+    graph, then the no-decay probability ||psi||^2, the remaining Rydberg
+    population P_R = sum_i <psi|n_i|psi> and the GHZ fidelity of the
+    unnormalised state (lost norm counts as fidelity zero)."""
+    import torch
+    from paper_2210_03763_amd import ttn
+    g = ttn.TTN(w.copy(gamma=gamma), device="cuda:0")
+    if warmup:
+        g.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    n2, _ = g.observables()
+    pop = g.rydberg_population()
+    F, _ = g.fidelity()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    return {"gamma": gamma, "steps": steps, "ms_per_step": round(ms, 3), "steps_per_s": round(1e3 / ms, 4),
+            "after_steps": warmup + steps, "norm2": n2, "rydberg_population_P_R": pop, "fidelity": F}
 
 
 def sample_flops_per_shot(w) -> float:
@@ -256,6 +287,10 @@ def main():
                     help="recorded steps of the forward+adjoint measurement (0: skip)")
     ap.add_argument("--sample-shots", type=int, default=1000000,
                     help="projective-measurement shots of the sampling measurement (0: skip)")
+    ap.add_argument("--open-gamma", type=float, default=0.02,
+                    help="decay rate of the open-system measurement (0: skip)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every step eagerly (for counter collection; kernels are the same)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -273,7 +308,8 @@ def main():
     fps = heff_flops_per_step(w)
     print(f"[bench] mixed run: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr, flush=True)
     gm, ms_mixed, prof, ms_prof, F_m, n2_m, E_m = run_gpu(w, args.steps, args.warmup,
-                                                          calib_mib=args.calib_copy_mib)
+                                                          calib_mib=args.calib_copy_mib,
+                                                          graphs=not args.no_graphs)
     print(f"[bench] mixed {ms_mixed:.1f} ms/step F={F_m:.12f}", file=sys.stderr, flush=True)
     k = prof.gemm_f32 if w.precision == ttn.PREC_FP32 else prof.gemm_f64
     dt = "fp32" if w.precision == ttn.PREC_FP32 else "fp64"
@@ -323,6 +359,10 @@ def main():
                 max(1e-9, adj["mixed"]["fwd_ms_per_step"] + adj["mixed"]["bwd_ms_per_step"])
             adj["mixed_speedup_fwd_adj"] = round(adj["mixed_speedup_fwd_adj"], 3)
         out["forward_adjoint"] = adj
+    if args.open_gamma > 0:
+        print(f"[bench] open system: gamma {args.open_gamma}, {args.steps} steps", file=sys.stderr, flush=True)
+        out["open_system"] = run_open(w, args.steps, args.warmup, args.open_gamma)
+        out["open_system"]["closed_ms_per_step"] = round(ms_mixed, 3)
     if args.sample_shots > 0:
         print(f"[bench] sampling: {args.sample_shots} shots", file=sys.stderr, flush=True)
         out["sampling"] = run_sampling(w, args.sample_shots)

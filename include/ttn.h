@@ -81,6 +81,11 @@ typedef struct {
     const double* dress_noise;  /* host complex stream G, node blocks level by
                                    level, l fastest; may be NULL if eps == 0 */
     int64_t dress_noise_len;    /* complex elements in dress_noise           */
+    double gamma;           /* Rydberg decay rate of the open system,
+                               Eq. (eq:hoqs): every site's local term gains
+                               -i gamma |r><r|, the state loses norm and the
+                               local exponentials switch from Lanczos to
+                               Arnoldi; 0 = closed system.  >= 0.          */
 } ttn_config;
 
 /* Per-step diagnostics, filled by ttn_tdvp_step when stats != NULL. */
@@ -118,6 +123,18 @@ int ttn_set_pulses(ttn_handle* h, int32_t n_seg, const double* seg_edges,
                    const double* omega, const double* delta, int32_t n_events,
                    const int32_t* ev_step, const int32_t* ev_site, const double* ev_u);
 
+/* The single-qubit drive of Eq. (eq:ham): Omega^x_i(t) sigma^x_i +
+ * Omega^z_i(t) sigma^z_i with sigma^x = |0><1| + |1><0| and sigma^z =
+ * |0><0| - |1><1| (zero on |r> and |leak>), piecewise constant on the
+ * segments of the last ttn_set_pulses call: omega_x, omega_z host
+ * [N][n_seg] (site-major), either may be NULL (zero); both NULL removes the
+ * channels.  Gates can then be driven as square pulses through the TDVP
+ * instead of exact gate events.  ttn_set_pulses resets the channels to
+ * zero; this call ends an adjoint recording (the adjoint differentiates
+ * Omega and Delta only).  TTN_ESTATE before ttn_set_pulses, TTN_EINVAL for
+ * non-finite values.  Allocates two small device arrays. */
+int ttn_set_qubit_pulses(ttn_handle* h, const double* omega_x, const double* omega_z);
+
 /* n_steps TDVP steps of size dt (dt must not change between calls).
  * stats: host array [n_steps] or NULL. */
 int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* stats);
@@ -131,6 +148,14 @@ int ttn_fidelity(ttn_handle* h, int32_t n_target, const int32_t* target_sites,
 
 /* ||psi||^2 and <psi|H|psi> with H at the last step's midpoint. */
 int ttn_observables(ttn_handle* h, double* norm2, double* energy);
+
+/* Total Rydberg population sum_i <psi|n_i|psi> of the current state (not
+ * normalised: with gamma > 0 it is the population of the surviving norm),
+ * the integrand of the integrated time in the Rydberg state T_R and, at the
+ * final time, the remaining population P_R (open-system section,
+ * definitions of P_R and T_R).  Uses the environments of the root, which
+ * every step leaves current.  Synchronises the stream. */
+int ttn_rydberg_population(ttn_handle* h, double* pop);
 
 /* <psi|O_site|psi> for a d x d complex operator (row-major O[a][b]). */
 int ttn_local_expectation(ttn_handle* h, int32_t site, const double* op, double out[2]);
@@ -162,7 +187,8 @@ int ttn_adjoint_query(const ttn_config* cfg, int32_t n_steps, int32_t ckpt_every
  * checkpoints in d_buf (caller-owned device memory of at least the queried
  * size, which must outlive the recording; TTN_ENOMEM if it is smaller).  A
  * later ttn_set_pulses ends the recording; steps beyond n_steps invalidate
- * it. */
+ * it.  TTN_EINVAL for an open system (gamma > 0): the adjoint assumes a
+ * Hermitian Hamiltonian. */
 int ttn_record_begin(ttn_handle* h, int32_t n_steps, int32_t ckpt_every, void* d_buf, size_t bytes);
 
 /* grad_omega, grad_delta (host [N][n_seg], overwritten) = dF * dF/dOmega,
@@ -246,9 +272,9 @@ int ttn_set_graphs(ttn_handle* h, int32_t enabled);
 
 /* Checks the launch plan of a configuration without a device: walks
  * initialisation, n_steps TDVP steps of a one-segment program with a gate on
- * every site (recorded for the adjoint), the fidelity, a local expectation,
- * a self overlap, the backward pass and a few sampled shots, and verifies
- * that every kernel
+ * every site (recorded for the adjoint when gamma = 0), the fidelity, a
+ * local expectation, a self overlap, the Rydberg population, the backward
+ * pass (gamma = 0) and a few sampled shots, and verifies that every kernel
  * operand stays inside its workspace or adjoint-buffer allocation.
  * No device memory is touched.  msg (may be NULL) receives "ok" or the first
  * violation.  Not thread safe with concurrent device calls of this library. */

@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE (same import rule as ttn_oracle).  For small lattices
 the TDVP oracle is pinned against psi_{n+1} = exp(-i H(t_n + dt/2) dt) psi_n
 with the full Hamiltonian of Eq. (eq:ham)/(eq:c6) (read as in ttn_oracle:
-Omega/2 on |1><r| + h.c., -Delta |r><r|, optional leak coupling, positive
+Omega/2 on |1><r| + h.c., -Delta |r><r|, optional leak coupling, the
+single-qubit channels Omega^x sigma^x + Omega^z sigma^z, positive
 C6/d^6 over pairs i < j, and -i gamma |r><r| per site for the open system of
 Eq. (eq:hoqs)) built as a sparse matrix on the product basis
 (site 0 the slowest index), and evolved with scipy's expm_multiply.  At
@@ -41,13 +42,20 @@ def _embed(op, site, N, d):
     return out
 
 
-def hamiltonian(pos, d, omega_t, delta_t, c6=1.0, r_cut=0.0, leak_ratio=0.0, gamma=0.0):
+def hamiltonian(pos, d, omega_t, delta_t, c6=1.0, r_cut=0.0, leak_ratio=0.0, gamma=0.0, omx_t=None,
+                omz_t=None):
     N = len(pos)
     X, n, Lk = _ops(d)
+    sx = np.zeros((d, d), complex)
+    sz = np.zeros((d, d), complex)
+    sx[0, 1] = sx[1, 0] = 1
+    sz[0, 0], sz[1, 1] = 1, -1
     H = sp.csr_matrix((d ** N, d ** N), dtype=complex)
     nsite = [_embed(n, s, N, d) for s in range(N)]
     for s in range(N):
         hl = omega_t[s] / 2 * (X + leak_ratio * Lk) - (delta_t[s] + 1j * gamma) * n
+        if omx_t is not None:
+            hl = hl + omx_t[s] * sx + omz_t[s] * sz
         if np.any(hl != 0):
             H = H + _embed(hl, s, N, d)
     for i in range(N):
@@ -92,7 +100,11 @@ def run(w, psi0, n_steps=None, step0=0, apply_final_events=True):
         sidx = pulse_index(w.seg_edges, t)
         om = w.omega[:, sidx] if sidx >= 0 else np.zeros(N)
         de = w.delta[:, sidx] if sidx >= 0 else np.zeros(N)
-        H = hamiltonian(w.pos_xy, d, om, de, w.c6, w.r_cut, w.leak_ratio, getattr(w, "gamma", 0.0))
+        ox = oz = None
+        if getattr(w, "omega_x", None) is not None:
+            ox = w.omega_x[:, sidx] if sidx >= 0 else np.zeros(N)
+            oz = w.omega_z[:, sidx] if sidx >= 0 else np.zeros(N)
+        H = hamiltonian(w.pos_xy, d, om, de, w.c6, w.r_cut, w.leak_ratio, getattr(w, "gamma", 0.0), ox, oz)
         psi = spla.expm_multiply(-1j * w.dt * H, psi)
     if apply_final_events:
         for (k, s, U) in w.events:

@@ -11,7 +11,8 @@ reader can check it against the paper by eye.
 What it computes (paper sections in brackets):
   * Hamiltonian [Sec. "Modeling 88Sr quantum computers", Eq. (eq:ham) and
     Eq. (eq:c6)]: per site h_i(t) = Omega_i/2 (|1><r| + |r><1|) - Delta_i |r><r|
-    (+ leak_ratio * Omega_i/2 (|leak><r| + |r><leak|) for d = 4), plus
+    (+ leak_ratio * Omega_i/2 (|leak><r| + |r><leak|) for d = 4)
+    + Omega^x_i sigma^x + Omega^z_i sigma^z on the qubit levels, plus
     sum_{i<j} V_ij n_i n_j with V_ij = C6 / |r_i - r_j|^6 (sign and the
     double count of the printed double sum read as a single positive sum
     over pairs), optional cutoff radius.
@@ -76,6 +77,17 @@ def local_ops(d: int):
     if d >= 4:
         Lk[3, 2] = Lk[2, 3] = 1.0
     return X, n, Lk
+
+
+def qubit_ops(d: int):
+    """sigma^x = |0><1| + |1><0| and sigma^z = |0><0| - |1><1| on the qubit
+    levels (Eq. (eq:ham)); zero on |r> and |leak>."""
+    sx = torch.zeros(d, d, dtype=CDT)
+    sz = torch.zeros(d, d, dtype=CDT)
+    sx[0, 1] = sx[1, 0] = 1.0
+    sz[0, 0] = 1.0
+    sz[1, 1] = -1.0
+    return sx, sz
 
 
 def vdw_matrix(pos: torch.Tensor, c6: float, r_cut: float) -> torch.Tensor:
@@ -344,12 +356,15 @@ class OracleTTN:
         self.gamma = float(gamma)
         self.V = vdw_matrix(torch.as_tensor(pos_xy, dtype=RDT), c6, r_cut)
         self.X, self.n, self.Lk = local_ops(d)
+        self.sx, self.sz = qubit_ops(d)
         self.leak_ratio = leak_ratio
         self.T: List[torch.Tensor] = [None] * self.tree.n_nodes
         self.up: Dict[int, dict] = {}
         self.down: Dict[int, dict] = {}
         self.omega_t = torch.zeros(n_sites, dtype=RDT)
         self.delta_t = torch.zeros(n_sites, dtype=RDT)
+        self.omx_t = torch.zeros(n_sites, dtype=RDT)
+        self.omz_t = torch.zeros(n_sites, dtype=RDT)
         self.stats = []
 
     # -- initial state --------------------------------------------------
@@ -408,15 +423,21 @@ class OracleTTN:
             self.T[u] = on_leg(tr.leg_in_parent(v), R, self.T[u])
 
     # -- Hamiltonian at the current time ----------------------------------
-    def set_time(self, seg_edges, omega, delta, t):
+    def set_time(self, seg_edges, omega, delta, t, omega_x=None, omega_z=None):
         om, de, _ = pulse_at(seg_edges, torch.as_tensor(omega, dtype=RDT),
                              torch.as_tensor(delta, dtype=RDT), t)
         self.omega_t, self.delta_t = om.clone(), de.clone()
+        zero = torch.zeros_like(torch.as_tensor(omega, dtype=RDT))
+        ox, oz, _ = pulse_at(seg_edges, zero if omega_x is None else torch.as_tensor(omega_x, dtype=RDT),
+                             zero if omega_z is None else torch.as_tensor(omega_z, dtype=RDT), t)
+        self.omx_t, self.omz_t = ox.clone(), oz.clone()
 
     def h_local(self, site):
         om = self.omega_t[site]
         de = self.delta_t[site]
         h = (om / 2) * (self.X + self.leak_ratio * self.Lk) - de * self.n
+        # single-qubit channels of Eq. (eq:ham) on {|0>, |1>}
+        h = h + self.omx_t[site] * self.sx + self.omz_t[site] * self.sz
         if self.gamma != 0.0:
             # open system: decay out of |r> as the non-Hermitian term -i gamma |r><r|
             h = h - 1j * self.gamma * self.n
@@ -718,7 +739,7 @@ def run(w, n_steps: Optional[int] = None, st: Optional[OracleTTN] = None, step0:
         for (k, s, U) in w.events:
             if k == n:
                 st.apply_gate(s, U)
-        st.set_time(edges, om, de, (n + 0.5) * w.dt)
+        st.set_time(edges, om, de, (n + 0.5) * w.dt, getattr(w, "omega_x", None), getattr(w, "omega_z", None))
         st.rebuild_up()
         st.sweep_fwd(tau)
         st.sweep_bwd(tau)

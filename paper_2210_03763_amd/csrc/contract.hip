@@ -188,13 +188,18 @@ __global__ void k_splitk_reduce(Gemm<R> g, int splits, const R* partial) {
 }
 
 // ---------------------------------------------------------------------------
-// MFMA contraction kernel (gfx950): complex C = A B as four real products per
-// 16x16x4 MFMA tile (Ar Br - Ai Bi, Ar Bi + Ai Br).  The matrix-core operands
-// are fed transposed (B^T as the first, A^T as the second) so that the output
-// lanes of each 16x16 tile run along m, the contiguous index of C.  Tiles of A
-// (BM x 16) and B (16 x BN) are staged through LDS; the next k-tile is fetched
-// into registers while the current one is multiplied.  A k-tile never crosses
-// a boundary of the outer contraction index (Kin % 16 == 0).
+// MFMA contraction kernel (gfx950).  Complex C = A B with three real
+// products per complex product (Gauss): P1 = Ar Br, P2 = Ai Bi,
+// P3 = (Ar + Ai)(Br + Bi), then Re C = P1 - P2 and Im C = P3 - P1 - P2 -- a
+// quarter fewer matrix-core operations than the four-product form, for a
+// third accumulator per output tile.  The matrix-core operands are fed
+// transposed (B^T as the first, A^T as the second) so that the output lanes
+// of each 16x16x4 tile run along m, the contiguous index of C.  Tiles of A
+// (BM x BK) and B (BK x BN) are staged through double-buffered LDS; the next
+// k-tile is fetched into registers while the current one is multiplied.  A
+// k-tile never crosses a boundary of the outer contraction index
+// (Kin % BK == 0).  The block holds WGM x WGN waves of (BM/WGM) x (BN/WGN)
+// outputs each.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -221,17 +226,18 @@ struct MfmaT<double> {
     static constexpr int PAD = 8;
 };
 
-template <typename R, int BM, int BN, bool AK, bool BKF>
-__global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, int tilesN, int splits,
-                                                       int kchunk, R* partial) {
+template <typename R, int BM, int BN, int WGM, int WGN, int MINB, int BK, bool AK, bool BKF>
+__global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, int tilesM, int tilesN,
+                                                                    int splits, int kchunk, R* partial) {
     if (g.skip && *g.skip) return;
-    constexpr int BK = 16;
-    constexpr int WM = BM / 2, WN = BN / 2;      // 2 x 2 waves
-    constexpr int TI = WM / 16, TJ = WN / 16;    // 16 x 16 tiles per wave
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int TI = WM / 16, TJ = WN / 16;
+    static_assert(TI >= 1 && TJ >= 1, "wave tile below 16 x 16");
     constexpr int PAD = MfmaT<R>::PAD;
-    constexpr int QA = BM * BK / 256, QB = BN * BK / 256;
+    constexpr int QA = BM * BK / NT, QB = BN * BK / NT;
+    static_assert(QA >= 1 && QB >= 1, "tile smaller than the block");
     typedef typename MfmaT<R>::acc_t acc_t;
-    // double-buffered k-tiles: [buffer][plane][k][index]
     __shared__ R As[2][2][BK][BM + PAD];
     __shared__ R Bs[2][2][BK][BN + PAD];
     int64_t bid = blockIdx.x;
@@ -250,17 +256,15 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, in
     const int kb = sp * kchunk;
     const int ke = min(K, kb + kchunk);
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-    const int wm0 = (wave % 2) * WM, wn0 = (wave / 2) * WN;
+    const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
     const R sa = g.conjA ? R(-1) : R(1), sb = g.conjB ? R(-1) : R(1);
     const int mlim = g.M - m0, nlim = g.N - n0;
 
-    // per-thread load slots (fixed across k-tiles); rows outside the matrix
-    // read row 0 of the tile and are zeroed by a mask (no divergent branches)
     int offA[QA], offB[QB];
     R mA[QA], mB[QB];
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
-        const int e = tid + 256 * q;
+        const int e = tid + NT * q;
         const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
         const bool ok = mm < mlim;
         mA[q] = ok ? R(1) : R(0);
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, in
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-        const int e = tid + 256 * q;
+        const int e = tid + NT * q;
         const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
         const bool ok = nn < nlim;
         mB[q] = ok ? R(1) : R(0);
@@ -293,28 +297,29 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, in
     auto stash = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
             As[buf][0][kk][mm] = pa[0][q];
             As[buf][1][kk][mm] = pa[1][q];
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
             Bs[buf][0][kk][nn] = pb[0][q];
             Bs[buf][1][kk][nn] = pb[1][q];
         }
     };
-    acc_t cre[TI][TJ], cim[TI][TJ];
+    acc_t c1[TI][TJ], c2[TI][TJ], c3[TI][TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
-            cre[i][j] = acc_t{0, 0, 0, 0};
-            cim[i][j] = acc_t{0, 0, 0, 0};
+            c1[i][j] = acc_t{0, 0, 0, 0};
+            c2[i][j] = acc_t{0, 0, 0, 0};
+            c3[i][j] = acc_t{0, 0, 0, 0};
         }
-    const int nt = (ke - kb) / BK;   // k-tiles of this split (K and kchunk are multiples of BK)
+    const int nt = (ke - kb) / BK;
     if (nt > 0) {
         fetch(kb);
         stash(0);
@@ -326,37 +331,30 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, in
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + lane / 16, c16 = lane % 16;
-            R br[TJ], bi[TJ], nbi[TJ], ar[TI], ai[TI];
+            R br[TJ], bi[TJ], bs[TJ], ar[TI], ai[TI], as[TI];
 #pragma unroll
             for (int j = 0; j < TJ; ++j) {
                 br[j] = Bs[cur][0][kr][wn0 + 16 * j + c16];
                 bi[j] = Bs[cur][1][kr][wn0 + 16 * j + c16];
-                nbi[j] = -bi[j];
+                bs[j] = br[j] + bi[j];
             }
 #pragma unroll
             for (int i = 0; i < TI; ++i) {
                 ar[i] = As[cur][0][kr][wm0 + 16 * i + c16];
                 ai[i] = As[cur][1][kr][wm0 + 16 * i + c16];
+                as[i] = ar[i] + ai[i];
             }
-            // output tile (j, i) holds C^T[n][m]: first operand from B, second
-            // from A; the four real products go out in two passes so that
-            // back-to-back MFMAs never share an accumulator
+            // the three products of one tile are independent: back-to-back
+            // MFMAs never share an accumulator
 #pragma unroll
             for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int j = 0; j < TJ; ++j) {
-                    cre[i][j] = MfmaT<R>::mfma(br[j], ar[i], cre[i][j]);
-                    cim[i][j] = MfmaT<R>::mfma(bi[j], ar[i], cim[i][j]);
-                }
-#pragma unroll
-            for (int i = 0; i < TI; ++i)
-#pragma unroll
-                for (int j = 0; j < TJ; ++j) {
-                    cre[i][j] = MfmaT<R>::mfma(nbi[j], ai[i], cre[i][j]);
-                    cim[i][j] = MfmaT<R>::mfma(br[j], ai[i], cim[i][j]);
+                    c1[i][j] = MfmaT<R>::mfma(br[j], ar[i], c1[i][j]);
+                    c2[i][j] = MfmaT<R>::mfma(bi[j], ai[i], c2[i][j]);
+                    c3[i][j] = MfmaT<R>::mfma(bs[j], as[i], c3[i][j]);
                 }
         }
-        // the other buffer was last read before the previous barrier
         if (t + 1 < nt) {
             stash(cur ^ 1);
             if (t + 2 < nt) fetch(kb + (t + 2) * BK);
@@ -376,9 +374,11 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, in
                 const int m = m0 + wm0 + 16 * i + lane % 16;
                 const int n = n0 + wn0 + 16 * j + MfmaT<R>::row(lane, r);
                 if (m >= g.M || n >= g.N) continue;
+                const R vre = c1[i][j][r] - c2[i][j][r];
+                const R vim = c3[i][j][r] - c1[i][j][r] - c2[i][j][r];
                 if (splits == 1) {
                     const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
-                    R re = g.alpha * cre[i][j][r], im = g.alpha * cim[i][j][r];
+                    R re = g.alpha * vre, im = g.alpha * vim;
                     if (g.beta) {
                         re += C[off];
                         im += C[off + g.c_plane];
@@ -386,8 +386,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_mfma(Gemm<R> g, int tilesM, in
                     C[off] = re;
                     C[off + g.c_plane] = im;
                 } else {
-                    P[m + (int64_t)g.M * n] = cre[i][j][r];
-                    P[MN + m + (int64_t)g.M * n] = cim[i][j][r];
+                    P[m + (int64_t)g.M * n] = vre;
+                    P[MN + m + (int64_t)g.M * n] = vim;
                 }
             }
 }
@@ -445,7 +445,7 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
     const int64_t nbatch = (int64_t)g.B1 * g.B2;
     const bool a_k = g.sak == 1 && g.sam != 1, b_k = g.sbk == 1 && g.sbn != 1;
     // per-element offsets inside a tile are 32-bit in the MFMA kernel
-    const bool off32 = (int64_t)128 * (g.sam + g.sbn) + 16 * (g.sak + g.sbk) + g.a_plane + g.b_plane < (1LL << 31);
+    const bool off32 = (int64_t)128 * (g.sam + g.sbn) + 32 * (g.sak + g.sbk) + g.a_plane + g.b_plane < (1LL << 31);
     const bool mfma_ok = K >= 16 && g.Kin % 16 == 0 && g.M >= 16 && g.N >= 16 && (g.sam == 1 || g.sak == 1) &&
                          (g.sbn == 1 || g.sbk == 1) && off32;
     if (mfma_ok) {
@@ -453,6 +453,9 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         const bool big = g.M >= 128 && g.N >= (sizeof(R) == 4 ? 128 : 64);
         const int BM = big ? 128 : 64;
         const int BN = big ? (sizeof(R) == 4 ? 128 : 64) : 64;
+        // FP32 large tiles take 32-wide k-tiles (half the barriers) where the
+        // inner contraction extent allows them
+        const int kq = (sizeof(R) == 4 && big && g.Kin % 32 == 0) ? 32 : 16;
         const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
         const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
         int splits = 1;
@@ -466,37 +469,42 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         }
         int kchunk = K;
         if (splits > 1) {
-            kchunk = ((ktiles + splits - 1) / splits) * 16;
+            kchunk = ((K / kq + splits - 1) / splits) * kq;
             splits = (K + kchunk - 1) / kchunk;
         }
-        const dim3 grid((unsigned)(tiles * splits)), blk(256);
+        const dim3 grid((unsigned)(tiles * splits));
         R* part = (R*)ws.partial;
         if (ev0) (void)hipEventRecord(ev0, s);
-#define TTN_MFMA_LAUNCH(bm, bn)                                                                              \
-    do {                                                                                                     \
-        if (a_k && b_k)                                                                                      \
-            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, true, true>), grid, blk, 0, s, g, tilesM, tilesN,    \
-                               splits, kchunk, part);                                                        \
-        else if (a_k)                                                                                        \
-            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, true, false>), grid, blk, 0, s, g, tilesM, tilesN,   \
-                               splits, kchunk, part);                                                        \
-        else if (b_k)                                                                                        \
-            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, false, true>), grid, blk, 0, s, g, tilesM, tilesN,   \
-                               splits, kchunk, part);                                                        \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, false, false>), grid, blk, 0, s, g, tilesM, tilesN,  \
-                               splits, kchunk, part);                                                        \
+#define TTN_MFMA_LAUNCH(bm, bn, wgm, wgn, minb, bk)                                                        \
+    do {                                                                                                   \
+        const dim3 blk(64 * wgm * wgn);                                                                    \
+        if (a_k && b_k)                                                                                    \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, wgm, wgn, minb, bk, true, true>), grid, blk, 0, s,   \
+                               g, tilesM, tilesN, splits, kchunk, part);                                   \
+        else if (a_k)                                                                                      \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, wgm, wgn, minb, bk, true, false>), grid, blk, 0, s,  \
+                               g, tilesM, tilesN, splits, kchunk, part);                                   \
+        else if (b_k)                                                                                      \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, wgm, wgn, minb, bk, false, true>), grid, blk, 0, s,  \
+                               g, tilesM, tilesN, splits, kchunk, part);                                   \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, wgm, wgn, minb, bk, false, false>), grid, blk, 0, s, \
+                               g, tilesM, tilesN, splits, kchunk, part);                                   \
     } while (0)
+        // large tiles: 8 waves (2 x 4) per block, one block per CU; small
+        // tiles: 4 waves (2 x 2), two blocks per CU
         if constexpr (sizeof(R) == 4) {
-            if (BM == 128)
-                TTN_MFMA_LAUNCH(128, 128);
+            if (BM == 128 && kq == 32)
+                TTN_MFMA_LAUNCH(128, 128, 2, 4, 1, 32);
+            else if (BM == 128)
+                TTN_MFMA_LAUNCH(128, 128, 2, 4, 1, 16);
             else
-                TTN_MFMA_LAUNCH(64, 64);
+                TTN_MFMA_LAUNCH(64, 64, 2, 2, 2, 16);
         } else {
             if (BM == 128)
-                TTN_MFMA_LAUNCH(128, 64);
+                TTN_MFMA_LAUNCH(128, 64, 2, 4, 1, 16);
             else
-                TTN_MFMA_LAUNCH(64, 64);
+                TTN_MFMA_LAUNCH(64, 64, 2, 2, 2, 16);
         }
 #undef TTN_MFMA_LAUNCH
         if (ev1) (void)hipEventRecord(ev1, s);

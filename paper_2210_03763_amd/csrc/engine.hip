@@ -67,6 +67,8 @@ struct ttn_handle {
     // configuration
     int N = 0, d = 0, chi = 0, m = 0, prec = 0;
     double c6 = 1, rcut = 0, leak = 0;
+    double gamma = 0;       // Rydberg decay rate (open system); > 0 selects Arnoldi
+    bool nonherm = false;
     hipStream_t stream = nullptr;
     std::string err;
     bool poisoned = false;
@@ -98,6 +100,7 @@ struct ttn_handle {
     int n_seg = 0;
     std::vector<double> edges;
     double *d_omega = nullptr, *d_delta = nullptr;
+    double *d_omx = nullptr, *d_omz = nullptr;   // single-qubit channels (both or neither)
     double* d_evU = nullptr;
     std::vector<Event> events;
     int64_t step_count = 0;
@@ -717,7 +720,7 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
         chk(h, h->Yf, n, "fp32 output");
         stage_f32(h, o, nullptr);
     }
-    lz_start(x, n, h->Vk, lz, h->red, nb, s);
+    lz_start(x, n, h->Vk, lz, h->red, nb, s, h->nonherm ? 1 : 0);
     if (n <= LZ_SMALL_N) {
         for (int j = 0; j < h->m; ++j) {
             apply_op_prec(h, o, h->Vk + 2 * n * j, h->W, &lz->done);
@@ -736,9 +739,23 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     }
 }
 
-// x <- exp(-i tau Op) x by Lanczos
+// x <- exp(-i tau Op) x by Lanczos (Arnoldi for the open system).  Small
+// operators run the whole evolution in one workgroup (FP64 in both modes).
 void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
+    if (n <= SMALL_EVOLVE_N &&
+        small_evolve_doubles(o.DL, o.DR, o.DP, o.sL, o.sR, h->m, o.Bb != nullptr, o.Wb != nullptr) <=
+            SMALL_EVOLVE_POOL) {
+        const int64_t L2 = (int64_t)o.DL * o.DL, R2 = (int64_t)o.DR * o.DR, P2 = (int64_t)o.DP * o.DP;
+        chk(h, x, 2 * n, "krylov input");
+        chk(h, o.Lb, 2 * (1 + o.sL) * L2, "L stack");
+        if (o.Wb && o.sR > 0) chk(h, o.Rb, 2 * (1 + o.sR) * R2, "R stack");
+        if (o.Bb) chk(h, o.Bb, 2 * (1 + o.sL) * R2, "B stack");
+        if (o.Wb) chk(h, o.Wb, 2 * (1 + o.sL + o.sR) * P2, "W stack");
+        small_evolve(o.Lb, o.Rb, o.Bb, o.Wb, o.DL, o.DR, o.DP, o.sL, o.sR, h->m, tau, LANCZOS_TOL, h->nonherm, x,
+                     h->st, h->stream);
+        return;
+    }
     lanczos_basis(h, o, x);
     lz_expm(h->lz, tau, h->st, h->stream);
     lz_combine(h->Vk, n, x, h->lz, h->stream);
@@ -882,7 +899,8 @@ void build_down_core(Ctx<R>& c, int leg, int DL, int DR, int DP, int sL, int sR,
 
 // In the mixed path the environment contractions run in complex FP32 on
 // FP32 copies of their operands; the FP32 results are made exactly
-// Hermitian while converted back into the FP64 environment store.
+// Hermitian while converted back into the FP64 environment store (all but
+// the block Hamiltonian of an open system, which is not Hermitian).
 void build_up(ttn_handle* h, int v) {
     Ctx<double> c{h, nullptr};
     const int DL = h->DL[v], DR = h->DR[v], DP = h->DP[v];
@@ -901,7 +919,7 @@ void build_up(ttn_handle* h, int v) {
         convert_d2f(Rb, h->Rf, 2 * (1 + sR) * R2, nullptr, h->stream);
         convert_d2f(h->Bstk, h->Bf, 2 * (1 + sL) * R2, nullptr, h->stream);
         build_up_core<float>(cf, DL, DR, DP, sL, sR, Qf, h->Lf, h->Rf, h->Bf, h->Xf, h->Yf, h->Ef);
-        herm_f2d(h->Ef, h->up[v], DP, 1 + sL + sR, h->stream);
+        herm_f2d(h->Ef, h->up[v], DP, 1 + sL + sR, h->stream, h->nonherm);
     } else {
         build_up_core<double>(c, DL, DR, DP, sL, sR, h->T[v], Lb, Rb, h->Bstk, h->X, h->W, h->up[v]);
     }
@@ -946,7 +964,7 @@ void build_down(ttn_handle* h, int cnode) {
             convert_d2f(Ab + 2 * L2, h->Bf + 2 * L2, 2 * (Alen - L2), nullptr, h->stream);
         build_down_core<float>(cf, leg, DL, DR, DP, sL, sR, Qf, h->Lf, h->Rf, Wb ? h->Wf : nullptr, h->Bf, h->Xf,
                                h->Yf, h->Ef);
-        herm_f2d(h->Ef, h->dn[cnode], Dc, 1 + (leg == 0 ? sL : sR), h->stream);
+        herm_f2d(h->Ef, h->dn[cnode], Dc, 1 + (leg == 0 ? sL : sR), h->stream, h->nonherm);
     } else {
         build_down_core<double>(c, leg, DL, DR, DP, sL, sR, h->T[u], Lb, Rb, Wb, Ab, h->X, h->W, h->dn[cnode]);
     }
@@ -1034,8 +1052,8 @@ int segment_at(const ttn_handle* h, double t) {
 }
 
 __global__ void k_leaf_blocks_seg(double* blk, const int* leaf_site, const double* om,
-                                  const double* de, int n_seg, int seg, int n_leaves, int d,
-                                  double leak) {
+                                  const double* de, const double* omx, const double* omz, int n_seg, int seg,
+                                  int n_leaves, int d, double leak, double gamma) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_leaves) return;
     const int s = leaf_site[k];
@@ -1055,6 +1073,14 @@ __global__ void k_leaf_blocks_seg(double* blk, const int* leaf_site, const doubl
         hh[2 + d * 3] += leak * o2;
     }
     hh[2 + d * 2] -= dl;   // -Delta |r><r|
+    hh[dd + 2 + d * 2] -= gamma;   // open system: -i gamma |r><r| (imaginary plane)
+    if (omx && seg >= 0) {         // Omega^x sigma^x + Omega^z sigma^z on {|0>, |1>}
+        const double ox = omx[(int64_t)s * n_seg + seg], oz = omz[(int64_t)s * n_seg + seg];
+        hh[0 + d * 1] += ox;
+        hh[1 + d * 0] += ox;
+        hh[0 + d * 0] += oz;
+        hh[1 + d * 1] -= oz;
+    }
     nn[2 + d * 2] = 1.0;
 }
 
@@ -1062,7 +1088,8 @@ void set_hamiltonian(ttn_handle* h, int seg) {
     h->cur_seg = seg;
     if (h->dry) return;
     hipLaunchKernelGGL(k_leaf_blocks_seg, dim3((h->N + 63) / 64), dim3(64), 0, h->stream, h->leafblk,
-                       h->d_leaf_site, h->d_omega, h->d_delta, h->n_seg, seg, h->N, h->d, h->leak);
+                       h->d_leaf_site, h->d_omega, h->d_delta, h->d_omx, h->d_omz, h->n_seg, seg, h->N, h->d,
+                       h->leak, h->gamma);
     h->cur_seg = seg;
 }
 
@@ -1208,6 +1235,30 @@ void observables(ttn_handle* h, double* norm2, double* energy) {
     dot_c(h, h->T[r], h->W, n, b);
     *norm2 = a[0];
     *energy = b[0];
+}
+
+// sum_i <psi|n_i|psi> with the centre at the root: the n_i of the sites below
+// each child link of the root are slots 1.. of that link's operator stack
+// (the leaf blocks when the root is a bottom node)
+void rydberg_population(ttn_handle* h, double* pop) {
+    const int r = h->root;
+    const int DL = h->DL[r], DR = h->DR[r], DP = h->DP[r];
+    const int sL = sites_left(h, r), sR = sL;
+    const int64_t n = nsize(h, r);
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR;
+    const double* Lb = child_block(h, r, 0);
+    const double* Rb = child_block(h, r, 1);
+    chk(h, h->Rq, 2 * L2, "left number operator");
+    chk(h, h->Cb, 2 * R2, "right number operator");
+    chk(h, h->W, 2 * n, "number operator image");
+    sum_mats(Lb + 2 * L2, DL, sL, h->Rq, h->stream);
+    sum_mats(Rb + 2 * R2, DR, sR, h->Cb, h->stream);
+    Ctx<double> c{h, nullptr};
+    leg_apply<double>(c, 0, h->Rq, 0, h->T[r], 0, h->W, 0, DL, DR, DP, 1, 0);
+    leg_apply<double>(c, 1, h->Cb, 0, h->T[r], 0, h->W, 0, DL, DR, DP, 1, 1);
+    double a[2];
+    dot_c(h, h->T[r], h->W, n, a);
+    *pop = a[0];
 }
 
 // product-state overlap <phi|psi>, phi given per leaf (planar d-vectors, already conjugated)
@@ -1370,7 +1421,8 @@ void validate(const ttn_config* c) {
         if (s < 0 || s >= c->n_sites || seen[s]) throw StatusError{TTN_EINVAL, "leaf order is not a permutation"};
         seen[s] = 1;
     }
-    if (!(c->dress_eps >= 0) || !std::isfinite(c->c6) || !std::isfinite(c->leak_ratio))
+    if (!(c->dress_eps >= 0) || !std::isfinite(c->c6) || !std::isfinite(c->leak_ratio) ||
+        !(c->gamma >= 0) || !std::isfinite(c->gamma))
         throw StatusError{TTN_EINVAL, "bad scalar parameter"};
     for (int i = 0; i < c->n_sites; ++i)
         for (int j = 0; j < i; ++j)
@@ -1387,6 +1439,8 @@ void setup_config(ttn_handle* h, const ttn_config* c) {
     h->c6 = c->c6;
     h->rcut = c->r_cut;
     h->leak = c->leak_ratio;
+    h->gamma = c->gamma;
+    h->nonherm = c->gamma != 0.0;
     h->leaf_site.assign(c->leaf_order, c->leaf_order + c->n_sites);
     build_tree(h);
 }
@@ -1540,7 +1594,7 @@ int ttn_set_pulses(ttn_handle* h, int32_t n_seg, const double* seg_edges, const 
                                             [p](const Region& r) { return r.lo == (uintptr_t)p; }),
                              h->regions.end());
         };
-        for (double** pp : {&h->d_omega, &h->d_delta, &h->d_evU}) {
+        for (double** pp : {&h->d_omega, &h->d_delta, &h->d_evU, &h->d_omx, &h->d_omz}) {
             if (*pp) {
                 drop_region(*pp);
                 if (!h->dry) HIPCHECK(hipFree(*pp));
@@ -1593,6 +1647,50 @@ int ttn_set_pulses(ttn_handle* h, int32_t n_seg, const double* seg_edges, const 
     }
 }
 
+int ttn_set_qubit_pulses(ttn_handle* h, const double* omega_x, const double* omega_z) {
+    if (!h) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (!h->d_omega) throw StatusError{TTN_ESTATE, "ttn_set_pulses must be called first"};
+        const int64_t cnt = (int64_t)h->N * h->n_seg;
+        for (const double* a : {omega_x, omega_z})
+            if (a)
+                for (int64_t i = 0; i < cnt; ++i)
+                    if (!std::isfinite(a[i])) throw StatusError{TTN_EINVAL, "non-finite pulse value"};
+        if (h->adj) h->adj->active = false;   // a recording is tied to one pulse table
+        for (double** pp : {&h->d_omx, &h->d_omz}) {
+            if (*pp) {
+                const uintptr_t lo = (uintptr_t)*pp;
+                h->regions.erase(std::remove_if(h->regions.begin(), h->regions.end(),
+                                                [lo](const Region& r) { return r.lo == lo; }),
+                                 h->regions.end());
+                if (!h->dry) HIPCHECK(hipFree(*pp));
+                *pp = nullptr;
+            }
+        }
+        if (!omega_x && !omega_z) return TTN_OK;
+        const int64_t ns = std::max<int64_t>(1, cnt);
+        std::vector<double> zero;
+        if (!omega_x || !omega_z) zero.assign(ns, 0.0);
+        const double* src[2] = {omega_x ? omega_x : zero.data(), omega_z ? omega_z : zero.data()};
+        double** dst[2] = {&h->d_omx, &h->d_omz};
+        for (int k = 0; k < 2; ++k) {
+            if (h->dry) {
+                const uintptr_t top = (h->regions.empty() ? 0 : h->regions.back().hi) + (uintptr_t(1) << 32);
+                *dst[k] = (double*)top;
+            } else {
+                HIPCHECK(hipMalloc(dst[k], ns * sizeof(double)));
+                if (cnt > 0) HIPCHECK(hipMemcpy(*dst[k], src[k], cnt * sizeof(double), hipMemcpyHostToDevice));
+            }
+            h->regions.push_back(Region{(uintptr_t)*dst[k], (uintptr_t)*dst[k] + ns * sizeof(double)});
+            sort_regions(h);
+        }
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
 int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* stats) {
     if (!h) return TTN_EINVAL;
     if (h->poisoned) return TTN_ESTATE;
@@ -1619,7 +1717,9 @@ int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* sta
                 std::memcpy(&o.min_r_diag, &s.min_rdiag_bits, sizeof(double));
                 o.min_krylov = s.min_krylov;
                 o.reserved = 0;
-                if (!h->dry && (!std::isfinite(o.norm2) || std::fabs(o.norm2 - 1.0) > 1e-6))
+                // closed system: the norm is conserved; open system: it may only decay
+                const bool drift = h->nonherm ? o.norm2 > 1.0 + 1e-6 : std::fabs(o.norm2 - 1.0) > 1e-6;
+                if (!h->dry && (!std::isfinite(o.norm2) || drift))
                     throw StatusError{TTN_ENUMERIC, "norm drift beyond 1e-6"};
             }
         }
@@ -1674,6 +1774,22 @@ int ttn_observables(ttn_handle* h, double* norm2, double* energy) {
             rebuild_up(h);
         }
         observables(h, norm2, energy);
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        return fail(h, e);
+    }
+}
+
+int ttn_rydberg_population(ttn_handle* h, double* pop) {
+    if (!h || !pop) return TTN_EINVAL;
+    if (h->poisoned) return TTN_ESTATE;
+    try {
+        if (h->cur_seg == -2) {
+            set_hamiltonian(h, h->d_omega ? segment_at(h, 0.0) : -1);
+            if (!h->d_omega) h->cur_seg = -1;
+            rebuild_up(h);
+        }
+        rydberg_population(h, pop);
         return TTN_OK;
     } catch (const StatusError& e) {
         return fail(h, e);
@@ -1852,11 +1968,20 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         h = make_dry_handle(cfg, bytes);
         const int N = h->N, d = h->d;
         // record the steps for the adjoint, then walk the backward pass too
+        // (closed systems only: the adjoint rejects an open system)
+        const bool adj = !h->nonherm;
         const int32_t k = std::max(1, n_steps / 2);
-        const size_t abytes = adjoint_bytes(h, n_steps, k);
-        void* afake = (void*)(uintptr_t(1) << 45);
-        rc = ttn_record_begin(h, n_steps, k, afake, abytes);
-        if (rc != TTN_OK) throw StatusError{rc, h->err};
+        {   // single-qubit channels on every site
+            std::vector<double> ones((size_t)N * h->n_seg, 1.0);
+            rc = ttn_set_qubit_pulses(h, ones.data(), ones.data());
+            if (rc != TTN_OK) throw StatusError{rc, h->err};
+        }
+        if (adj) {
+            const size_t abytes = adjoint_bytes(h, n_steps, k);
+            void* afake = (void*)(uintptr_t(1) << 45);
+            rc = ttn_record_begin(h, n_steps, k, afake, abytes);
+            if (rc != TTN_OK) throw StatusError{rc, h->err};
+        }
         std::vector<ttn_step_stats> stats(std::max(1, n_steps));
         rc = ttn_tdvp_step(h, 0.01, n_steps, stats.data());
         if (rc != TTN_OK) throw StatusError{rc, h->err};
@@ -1870,9 +1995,13 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         if (rc != TTN_OK) throw StatusError{rc, h->err};
         rc = ttn_overlap(h, h, ov);
         if (rc != TTN_OK) throw StatusError{rc, h->err};
-        std::vector<double> go((size_t)N * h->n_seg), gd((size_t)N * h->n_seg);
-        rc = ttn_backward(h, N, all.data(), 1.0, go.data(), gd.data());
+        rc = ttn_rydberg_population(h, ov);
         if (rc != TTN_OK) throw StatusError{rc, h->err};
+        if (adj) {
+            std::vector<double> go((size_t)N * h->n_seg), gd((size_t)N * h->n_seg);
+            rc = ttn_backward(h, N, all.data(), 1.0, go.data(), gd.data());
+            if (rc != TTN_OK) throw StatusError{rc, h->err};
+        }
         size_t sbytes = 0;
         rc = ttn_sample_query(h, 3, &sbytes);
         if (rc != TTN_OK) throw StatusError{rc, h->err};
@@ -1957,6 +2086,7 @@ int ttn_record_begin(ttn_handle* h, int32_t n_steps, int32_t ckpt_every, void* d
     if (h->poisoned) return TTN_ESTATE;
     try {
         if (!h->d_omega && !h->dry) throw StatusError{TTN_ESTATE, "ttn_set_pulses must be called first"};
+        if (h->nonherm) throw StatusError{TTN_EINVAL, "the adjoint needs a Hermitian Hamiltonian (gamma = 0)"};
         record_begin(h, n_steps, ckpt_every, d_buf, bytes);
         if (!h->dry) HIPCHECK(hipGetLastError());
         return TTN_OK;
@@ -1999,6 +2129,8 @@ int ttn_destroy(ttn_handle* h) {
         if (h->d_omega) (void)hipFree(h->d_omega);
         if (h->d_delta) (void)hipFree(h->d_delta);
         if (h->d_evU) (void)hipFree(h->d_evU);
+        if (h->d_omx) (void)hipFree(h->d_omx);
+        if (h->d_omz) (void)hipFree(h->d_omz);
     }
     delete h;
     return TTN_OK;

@@ -94,13 +94,14 @@ __global__ void k_sum_partial(const double* partial, int nb, double* out, const 
     if (threadIdx.x == 0) *out = s;
 }
 
-__global__ void k_lz_begin(const double* partial, int nb, LanczosDev* lz) {
+__global__ void k_lz_begin(const double* partial, int nb, LanczosDev* lz, int nonherm) {
     const double s = wave_sum_partials(partial, nb);
     if (threadIdx.x == 0) {
         lz->beta0 = sqrt(s);
         lz->zero = (s == 0.0) ? 1 : 0;
         lz->done = lz->zero;
         lz->m_eff = 0;
+        lz->nonherm = nonherm;
     }
 }
 
@@ -170,6 +171,18 @@ __global__ void k_multidot_final(const double* partial, int nb, int kcount, Lanc
         if (k == alpha_index) {
             lz->alpha[k] = re;
             lz->m_eff = k + 1;
+        }
+        if (lz->nonherm) {
+            // Hessenberg column kcount - 1: the first pass (alpha_index >= 0)
+            // sets it, the second Gram-Schmidt pass adds its projections
+            double* hp = lz->hs + 2 * ((kcount - 1) * KRYLOV_MAX + k);
+            if (alpha_index >= 0) {
+                hp[0] = re;
+                hp[1] = im;
+            } else {
+                hp[0] += re;
+                hp[1] += im;
+            }
         }
     }
 }
@@ -267,6 +280,8 @@ __global__ __launch_bounds__(256) void k_lz_iter_small(double* V, int j, int m, 
         lz->alpha[j] = c[2 * j];
         lz->m_eff = j + 1;
     }
+    const int nonherm = lz->nonherm;
+    if (nonherm && threadIdx.x < 2 * kc) lz->hs[2 * j * KRYLOV_MAX + threadIdx.x] = c[threadIdx.x];
     if (j == m - 1) return;
     // subtract, second projection
 #pragma unroll
@@ -294,6 +309,7 @@ __global__ __launch_bounds__(256) void k_lz_iter_small(double* V, int j, int m, 
     t = block_sum32(a, sh32);
     __syncthreads();
     if (threadIdx.x < 32) c[threadIdx.x] = t;
+    if (nonherm && threadIdx.x < 2 * kc) lz->hs[2 * j * KRYLOV_MAX + threadIdx.x] += t;
     __syncthreads();
     // subtract again, norm
     double nrm[32];
@@ -353,8 +369,90 @@ __global__ void k_lz_beta(const double* partial, int nb, LanczosDev* lz, int j, 
 // of size m_eff: the Taylor series of exp(B/s), B = -i tau T, applied s times
 // to the vector, with s chosen so that ||B/s||_1 <= 1/4 (terms are summed
 // until they stop changing the result in double precision).
-__global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
-    if (threadIdx.x != 0 || lz->zero) return;
+// y = exp(-i tau H) e_1 for the complex upper Hessenberg H of an Arnoldi
+// basis (columns in hs, subdiagonal beta) of size m_eff: the same scaled
+// Taylor series, one thread per row of H for the products H term.
+__device__ void lz_expm_hessenberg(LanczosDev* lz, double tau, StepDev* st) {
+    constexpr int KM = KRYLOV_MAX;
+    __shared__ double Hr[KM][KM + 1], Hi[KM][KM + 1];
+    __shared__ double tr[KM], ti[KM], wr[KM], wi[KM], vr[KM], vi[KM];
+    const int m = lz->m_eff, t = threadIdx.x;
+    for (int e = t; e < KM * KM; e += blockDim.x) {
+        const int row = e % KM, col = e / KM;
+        double a = 0.0, b = 0.0;
+        if (row < m && col < m) {
+            if (row <= col) {
+                a = lz->hs[2 * (col * KM + row)];
+                b = lz->hs[2 * (col * KM + row) + 1];
+            } else if (row == col + 1) {
+                a = lz->beta[col];
+            }
+        }
+        Hr[row][col] = a;
+        Hi[row][col] = b;
+    }
+    if (t < KM) {
+        vr[t] = t == 0 ? 1.0 : 0.0;
+        vi[t] = 0.0;
+    }
+    __syncthreads();
+    // 1-norm bound of tau H: the largest column sum
+    double nrm = 0;
+    for (int col = 0; col < m; ++col) {
+        double cs = 0;
+        for (int row = 0; row < m; ++row) cs += fabs(Hr[row][col]) + fabs(Hi[row][col]);
+        nrm = cs > nrm ? cs : nrm;
+    }
+    nrm *= fabs(tau);
+    int ns = (int)ceil(nrm / 0.25);
+    if (ns < 1) ns = 1;
+    const double h = tau / ns;
+    for (int rep = 0; rep < ns; ++rep) {
+        if (t < KM) {
+            tr[t] = wr[t] = vr[t];
+            ti[t] = wi[t] = vi[t];
+        }
+        __syncthreads();
+        for (int k = 1; k <= 40; ++k) {
+            // term <- (-i h H term) / k
+            double sr = 0, si = 0;
+            if (t < m)
+                for (int c = 0; c < m; ++c) {
+                    sr += Hr[t][c] * tr[c] - Hi[t][c] * ti[c];
+                    si += Hr[t][c] * ti[c] + Hi[t][c] * tr[c];
+                }
+            __syncthreads();
+            const double f = h / k;
+            if (t < m) {
+                tr[t] = f * si;
+                ti[t] = -f * sr;
+                wr[t] += tr[t];
+                wi[t] += ti[t];
+            }
+            __syncthreads();
+            double tmax = 0, wmax = 0;
+            for (int i = 0; i < m; ++i) {
+                const double ta = fabs(tr[i]) + fabs(ti[i]), wa = fabs(wr[i]) + fabs(wi[i]);
+                tmax = ta > tmax ? ta : tmax;
+                wmax = wa > wmax ? wa : wmax;
+            }
+            if (tmax <= 1e-18 * wmax) break;   // the same decision in every thread
+        }
+        if (t < KM) {
+            vr[t] = wr[t];
+            vi[t] = wi[t];
+        }
+        __syncthreads();
+    }
+    if (t < KM) {
+        lz->y[2 * t] = t < m ? vr[t] : 0.0;
+        lz->y[2 * t + 1] = t < m ? vi[t] : 0.0;
+    }
+    if (t == 0) atomicMin(&st->min_krylov, m);
+}
+
+// The tridiagonal case (one thread).
+__device__ void lz_expm_tridiag(LanczosDev* lz, double tau, StepDev* st) {
     const int m = lz->m_eff;
     double al[KRYLOV_MAX], be[KRYLOV_MAX];
 #pragma unroll
@@ -430,6 +528,240 @@ __global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
     atomicMin(&st->min_krylov, m);
 }
 
+__global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
+    if (lz->zero) return;
+    if (lz->nonherm) {
+        lz_expm_hessenberg(lz, tau, st);
+        return;
+    }
+    if (threadIdx.x == 0) lz_expm_tridiag(lz, tau, st);
+}
+
+// ---------------------------------------------------------------------------
+// Fused evolution of a small operator: x <- exp(-i tau Op) x for an
+// effective Hamiltonian with n = DL DR DP <= SMALL_EVOLVE_N entries in one
+// workgroup, every vector and operator stack in LDS, FP64 throughout: the
+// matvec (the same four stages as the GEMM path), the Krylov recursion with
+// two Gram-Schmidt passes, the small exponential and the recombination.
+// Replaces about a hundred launches per evolution of the bottom nodes and
+// their bonds.
+// ---------------------------------------------------------------------------
+constexpr int SMALL_THREADS = 256;
+
+// y = Op x; S holds the left (U_k = L_k x_L x, k = 1..sL) and right (Z_j =
+// R_j x_R x) images, slot stride 2n
+__device__ void small_matvec(const double* L, const double* Rr, const double* B, const double* W, int DL, int DR,
+                             int DP, int sL, int sR, const double* x, double* S, double* y) {
+    const int n = DL * DR * DP;
+    const int L2 = DL * DL, R2 = DR * DR, P2 = DP * DP;
+    const int nz = (W && sR > 0) ? sR : 0;
+    for (int e = threadIdx.x; e < n * (sL + nz); e += blockDim.x) {
+        const int k = e / n, i = e % n;
+        const int l = i % DL, r = (i / DL) % DR, p = i / (DL * DR);
+        double ar = 0, ai = 0;
+        if (k < sL) {
+            const double* op = L + 2 * L2 * (k + 1);
+            for (int q = 0; q < DL; ++q) {
+                const double orr = op[l + DL * q], oi = op[L2 + l + DL * q];
+                const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
+                ar += orr * xr - oi * xi;
+                ai += orr * xi + oi * xr;
+            }
+        } else {
+            const double* op = Rr + 2 * R2 * (k - sL + 1);
+            for (int q = 0; q < DR; ++q) {
+                const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
+                const double xr = x[l + DL * (q + DR * p)], xi = x[n + l + DL * (q + DR * p)];
+                ar += orr * xr - oi * xi;
+                ai += orr * xi + oi * xr;
+            }
+        }
+        S[2 * n * k + i] = ar;
+        S[2 * n * k + n + i] = ai;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int l = i % DL, r = (i / DL) % DR, p = i / (DL * DR);
+        double ar = 0, ai = 0;
+        for (int q = 0; q < DL; ++q) {   // block Hamiltonian of the left leg
+            const double orr = L[l + DL * q], oi = L[L2 + l + DL * q];
+            const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
+            ar += orr * xr - oi * xi;
+            ai += orr * xi + oi * xr;
+        }
+        if (B)
+            for (int k = 0; k <= sL; ++k) {   // right leg: H_R x + sum_i A_i U_i
+                const double* op = B + 2 * R2 * k;
+                const double* src = k == 0 ? x : S + 2 * n * (k - 1);
+                for (int q = 0; q < DR; ++q) {
+                    const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
+                    const double xr = src[l + DL * (q + DR * p)], xi = src[n + l + DL * (q + DR * p)];
+                    ar += orr * xr - oi * xi;
+                    ai += orr * xi + oi * xr;
+                }
+            }
+        if (W)
+            for (int k = 0; k <= sL + nz; ++k) {   // parent leg: H_P x + sum W U + sum W Z
+                const double* op = W + 2 * P2 * k;
+                const double* src = k == 0 ? x : S + 2 * n * (k - 1);
+                for (int q = 0; q < DP; ++q) {
+                    const double orr = op[p + DP * q], oi = op[P2 + p + DP * q];
+                    const double xr = src[l + DL * (r + DR * q)], xi = src[n + l + DL * (r + DR * q)];
+                    ar += orr * xr - oi * xi;
+                    ai += orr * xi + oi * xr;
+                }
+            }
+        y[i] = ar;
+        y[n + i] = ai;
+    }
+    __syncthreads();
+}
+
+// c_k = <v_k, w> for k < kc (planar vectors of n in LDS), into c[2 kc] (LDS)
+__device__ void small_project(const double* V, int kc, const double* w, int n, double* c, double* sh32) {
+    double a[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a[k] = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double wr = w[i], wi = w[n + i];
+#pragma unroll
+        for (int k = 0; k < KRYLOV_MAX; ++k)
+            if (k < kc) {
+                const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
+                a[2 * k] += vr * wr + vi * wi;
+                a[2 * k + 1] += vr * wi - vi * wr;
+            }
+    }
+    const double t = block_sum32(a, sh32);
+    __syncthreads();
+    if (threadIdx.x < 2 * kc) c[threadIdx.x] = t;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL, const double* gR, const double* gB,
+                                                             const double* gW, int DL, int DR, int DP, int sL,
+                                                             int sR, int m, double tau, double tol, int nonherm,
+                                                             double* x, StepDev* st) {
+    __shared__ double pool[SMALL_EVOLVE_POOL];
+    __shared__ LanczosDev lz;
+    __shared__ double sh32[4 * 32];
+    __shared__ double c[32];
+    __shared__ double s_beta;
+    __shared__ int s_stop;
+    const int n = DL * DR * DP;
+    const int L2 = DL * DL, R2 = DR * DR, P2 = DP * DP;
+    const int nz = (gW && sR > 0) ? sR : 0;
+    // carve: V[(m+1)], w, S[sL + nz], L, R, B, W
+    double* V = pool;
+    double* w = V + 2 * n * (m + 1);
+    double* S = w + 2 * n;
+    double* L = S + 2 * n * (sL + nz);
+    double* Rr = L + 2 * L2 * (1 + sL);
+    double* B = Rr + (nz ? 2 * R2 * (1 + sR) : 0);
+    double* W = B + (gB ? 2 * R2 * (1 + sL) : 0);
+    for (int e = threadIdx.x; e < 2 * L2 * (1 + sL); e += blockDim.x) L[e] = gL[e];
+    if (nz)
+        for (int e = threadIdx.x; e < 2 * R2 * (1 + sR); e += blockDim.x) Rr[e] = gR[e];
+    if (gB)
+        for (int e = threadIdx.x; e < 2 * R2 * (1 + sL); e += blockDim.x) B[e] = gB[e];
+    if (gW)
+        for (int e = threadIdx.x; e < 2 * P2 * (1 + sL + sR); e += blockDim.x) W[e] = gW[e];
+    // v_0 = x / ||x||
+    double a[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a[k] = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double xr = x[i], xi = x[n + i];
+        w[i] = xr;
+        w[n + i] = xi;
+        a[0] += xr * xr + xi * xi;
+    }
+    double t = block_sum32(a, sh32);
+    if (threadIdx.x == 0) {
+        lz.beta0 = sqrt(t);
+        lz.zero = t == 0.0 ? 1 : 0;
+        lz.done = lz.zero;
+        lz.m_eff = 0;
+        lz.nonherm = nonherm;
+    }
+    __syncthreads();
+    if (lz.zero) return;   // x = 0 stays 0
+    {
+        const double inv = 1.0 / lz.beta0;
+        for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) V[i] = w[i] * inv;
+    }
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        const int kc = j + 1;
+        small_matvec(L, nz ? Rr : nullptr, gB ? B : nullptr, gW ? W : nullptr, DL, DR, DP, sL, sR, V + 2 * n * j, S,
+                     w);
+        small_project(V, kc, w, n, c, sh32);
+        if (threadIdx.x == 0) {
+            lz.alpha[j] = c[2 * j];
+            lz.m_eff = j + 1;
+        }
+        if (nonherm && threadIdx.x < 2 * kc) lz.hs[2 * j * KRYLOV_MAX + threadIdx.x] = c[threadIdx.x];
+        if (j == m - 1) break;
+        // w -= V c, second projection, w -= V c'
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                double wr = w[i], wi = w[n + i];
+                for (int k = 0; k < kc; ++k) {
+                    const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
+                    wr -= c[2 * k] * vr - c[2 * k + 1] * vi;
+                    wi -= c[2 * k] * vi + c[2 * k + 1] * vr;
+                }
+                w[i] = wr;
+                w[n + i] = wi;
+            }
+            __syncthreads();
+            if (pass == 0) {
+                small_project(V, kc, w, n, c, sh32);
+                if (nonherm && threadIdx.x < 2 * kc) lz.hs[2 * j * KRYLOV_MAX + threadIdx.x] += c[threadIdx.x];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k) a[k] = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) a[0] += w[i] * w[i] + w[n + i] * w[n + i];
+        t = block_sum32(a, sh32);
+        if (threadIdx.x == 0) {
+            const double b = sqrt(t);
+            const double bprev = j > 0 ? lz.beta[j - 1] : 0.0;
+            const bool stop = !(b > tol * (fabs(lz.alpha[j]) + bprev));
+            if (stop)
+                lz.done = 1;
+            else
+                lz.beta[j] = b;
+            s_stop = stop;
+            s_beta = b;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        const double inv = 1.0 / s_beta;
+        for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) V[2 * n * (j + 1) + i] = w[i] * inv;
+        __syncthreads();
+    }
+    // y = exp(-i tau H_m) e_1, then x = beta0 sum_k y_k v_k
+    if (nonherm) {
+        lz_expm_hessenberg(&lz, tau, st);
+    } else if (threadIdx.x == 0) {
+        lz_expm_tridiag(&lz, tau, st);
+    }
+    __syncthreads();
+    const int me = lz.m_eff;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double re = 0, im = 0;
+        for (int k = 0; k < me; ++k) {
+            const double yr = lz.y[2 * k] * lz.beta0, yi = lz.y[2 * k + 1] * lz.beta0;
+            const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
+            re += yr * vr - yi * vi;
+            im += yr * vi + yi * vr;
+        }
+        x[i] = re;
+        x[n + i] = im;
+    }
+}
+
 __global__ void k_lz_combine(const double* V, int64_t n, double* out, const LanczosDev* lz) {
     if (lz->zero) return;
     __shared__ double y[2 * KRYLOV_MAX];
@@ -465,11 +797,11 @@ void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_
 }
 
 void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
-              hipStream_t s) {
+              hipStream_t s, int nonherm) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, x, n, partial,
                        (const int*)nullptr);
-    hipLaunchKernelGGL(k_lz_begin, dim3(1), dim3(64), 0, s, partial, nb, lz);
+    hipLaunchKernelGGL(k_lz_begin, dim3(1), dim3(64), 0, s, partial, nb, lz, nonherm);
     hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, x, n, v0, lz, 1, 0);
 }
 
@@ -520,6 +852,22 @@ void lz_expm(LanczosDev* lz, double tau, StepDev* st, hipStream_t s) {
     hipLaunchKernelGGL(k_lz_expm, dim3(1), dim3(64), 0, s, lz, tau, st);
 }
 
+int64_t small_evolve_doubles(int DL, int DR, int DP, int sL, int sR, int m, bool hasB, bool hasW) {
+    const int64_t n = (int64_t)DL * DR * DP;
+    const int64_t nz = (hasW && sR > 0) ? sR : 0;
+    return 2 * n * (m + 1) + 2 * n + 2 * n * (sL + nz) + 2 * (int64_t)DL * DL * (1 + sL) +
+           (nz ? 2 * (int64_t)DR * DR * (1 + sR) : 0) + (hasB ? 2 * (int64_t)DR * DR * (1 + sL) : 0) +
+           (hasW ? 2 * (int64_t)DP * DP * (1 + sL + sR) : 0);
+}
+
+void small_evolve(const double* L, const double* R, const double* B, const double* W, int DL, int DR, int DP,
+                  int sL, int sR, int m, double tau, double tol, bool nonherm, double* x, StepDev* st,
+                  hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_small_evolve, dim3(1), dim3(SMALL_THREADS), 0, s, L, R, B, W, DL, DR, DP, sL, sR, m, tau,
+                       tol, nonherm ? 1 : 0, x, st);
+}
+
 void lz_combine(const double* V, int64_t n, double* out, LanczosDev* lz, hipStream_t s) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_lz_combine, dim3(grid_for(n)), dim3(256), 0, s, V, n, out, lz);
@@ -562,24 +910,43 @@ __global__ void k_transpose(const double* x, double* y, int rows, int cols) {
         y[n + c + (int64_t)cols * r] = x[n + e];
     }
 }
-__global__ void k_herm_f2d(const float* in, double* out, int D, int count) {
+__global__ void k_herm_f2d(const float* in, double* out, int D, int count, int raw_first) {
     const int64_t D2 = (int64_t)D * D, total = D2 * count;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = e / D2, ab = e % D2;
         const int a = (int)(ab % D), b = (int)(ab / D);
         const float* m = in + 2 * D2 * k;
+        if (k == 0 && raw_first) {
+            out[ab] = (double)m[ab];
+            out[D2 + ab] = (double)m[D2 + ab];
+            continue;
+        }
         const int64_t t = b + (int64_t)D * a;
         out[2 * D2 * k + ab] = 0.5 * ((double)m[ab] + (double)m[t]);
         out[2 * D2 * k + D2 + ab] = 0.5 * ((double)m[D2 + ab] - (double)m[D2 + t]);
     }
 }
+__global__ void k_sum_mats(const double* src, int64_t D2, int count, double* dst) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 2 * D2;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int k = 0; k < count; ++k) a += src[2 * D2 * k + e];
+        dst[e] = a;
+    }
+}
 }  // namespace
 
-void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s) {
+void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s, bool raw_first) {
     if (g_dry_run) return;
     const int64_t total = (int64_t)D * D * count;
-    hipLaunchKernelGGL(k_herm_f2d, dim3(grid_for(total)), dim3(256), 0, s, in, out, D, count);
+    hipLaunchKernelGGL(k_herm_f2d, dim3(grid_for(total)), dim3(256), 0, s, in, out, D, count, raw_first ? 1 : 0);
+}
+
+void sum_mats(const double* src, int D, int count, double* dst, hipStream_t s) {
+    if (g_dry_run) return;
+    const int64_t D2 = (int64_t)D * D;
+    hipLaunchKernelGGL(k_sum_mats, dim3(grid_for(2 * D2)), dim3(256), 0, s, src, D2, count, dst);
 }
 
 void convert_d2f(const double* x, float* y, int64_t count, const int* skip, hipStream_t s) {

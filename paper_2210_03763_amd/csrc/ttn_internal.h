@@ -69,7 +69,10 @@ struct LanczosDev {
     int m_eff;
     int done;
     int zero;
-    int pad;
+    int nonherm;     // Arnoldi: keep the whole Hessenberg projection in hs
+    // hs[2 (j KRYLOV_MAX + i)] = H[i][j] (re, im) for i <= j (Arnoldi only;
+    // the subdiagonal is beta)
+    double hs[2 * KRYLOV_MAX * KRYLOV_MAX];
 };
 
 // Step-level device flags and statistics.
@@ -83,8 +86,11 @@ struct StepDev {
 // reductions / vector kernels (double master vectors)
 void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_sum,
                const int* skip, hipStream_t s);
+// nonherm != 0 starts an Arnoldi basis (non-Hermitian operator): the
+// projections of both Gram-Schmidt passes are kept as Hessenberg columns and
+// lz_expm exponentiates the Hessenberg matrix instead of the tridiagonal one
 void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
-              hipStream_t s);
+              hipStream_t s, int nonherm = 0);
 void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
                 LanczosDev* lz, int alpha_index, hipStream_t s);
 void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s);
@@ -101,6 +107,19 @@ void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double*
 constexpr int64_t LZ_SMALL_N = 1024;
 void lz_iter_small(double* V, int j, int m, double* w, int64_t n, LanczosDev* lz, double tol, hipStream_t s);
 void lz_expm(LanczosDev* lz, double tau, StepDev* st, hipStream_t s);
+// x <- exp(-i tau Op) x in one workgroup for small operators (the four
+// matvec stages, Krylov recursion with two Gram-Schmidt passes, exponential
+// and recombination, all in LDS, FP64): usable when n = DL DR DP <=
+// SMALL_EVOLVE_N and small_evolve_doubles(...) <= SMALL_EVOLVE_POOL.
+// L: [1 + sL] left stack; R: right stack (only its N_j slots are read, and
+// only when W != nullptr); B: [1 + sL] right-leg stack or nullptr; W:
+// [1 + sL + sR] parent-leg stack or nullptr (the root).
+constexpr int64_t SMALL_EVOLVE_N = 1024;
+constexpr int SMALL_EVOLVE_POOL = 16384;   // doubles of LDS for vectors and stacks
+int64_t small_evolve_doubles(int DL, int DR, int DP, int sL, int sR, int m, bool hasB, bool hasW);
+void small_evolve(const double* L, const double* R, const double* B, const double* W, int DL, int DR, int DP,
+                  int sL, int sR, int m, double tau, double tol, bool nonherm, double* x, StepDev* st,
+                  hipStream_t s);
 void lz_combine(const double* V, int64_t n, double* out, LanczosDev* lz, hipStream_t s);
 
 // conversions and copies
@@ -109,8 +128,11 @@ void convert_f2d(const float* x, double* y, int64_t count, const int* skip, hipS
 void copy_d(const double* x, double* y, int64_t count, const int* skip, hipStream_t s);
 void transpose_c(const double* x, double* y, int rows, int cols, hipStream_t s);
 void fill_zero_d(double* y, int64_t count, hipStream_t s);
-// out_k = (in_k + in_k^H) / 2 for `count` planar D x D FP32 matrices, into FP64
-void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s);
+// out_k = (in_k + in_k^H) / 2 for `count` planar D x D FP32 matrices, into FP64;
+// with raw_first the first matrix is converted unchanged (a non-Hermitian block)
+void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s, bool raw_first = false);
+// dst = sum_{k < count} src_k for planar D x D FP64 matrices stored one after another
+void sum_mats(const double* src, int D, int count, double* dst, hipStream_t s);
 
 // Cholesky of a Hermitian D x D Gram matrix G (planar, column-major):
 // G = L L^H.  Writes Linv (lower, L^{-1}) and R = L^H (upper), or R = L^H * Rprev

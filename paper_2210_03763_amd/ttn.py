@@ -34,7 +34,8 @@ class Config(C.Structure):
                 ("c6", C.c_double), ("r_cut", C.c_double), ("leak_ratio", C.c_double),
                 ("pos_xy", C.POINTER(C.c_double)), ("leaf_order", C.POINTER(C.c_int32)),
                 ("init_product", C.POINTER(C.c_double)), ("dress_eps", C.c_double),
-                ("dress_noise", C.POINTER(C.c_double)), ("dress_noise_len", C.c_int64)]
+                ("dress_noise", C.POINTER(C.c_double)), ("dress_noise_len", C.c_int64),
+                ("gamma", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -63,10 +64,12 @@ def lib():
             "ttn_workspace_query": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_size_t)]),
             "ttn_init": (C.c_int, [C.POINTER(Config), P, C.c_size_t, P, C.POINTER(P)]),
             "ttn_set_pulses": (C.c_int, [P, I32, DP, DP, DP, I32, IP, IP, DP]),
+            "ttn_set_qubit_pulses": (C.c_int, [P, DP, DP]),
             "ttn_tdvp_step": (C.c_int, [P, D, I32, C.POINTER(StepStats)]),
             "ttn_fidelity": (C.c_int, [P, I32, IP, DP, DP]),
             "ttn_observables": (C.c_int, [P, DP, DP]),
             "ttn_local_expectation": (C.c_int, [P, I32, DP, DP]),
+            "ttn_rydberg_population": (C.c_int, [P, DP]),
             "ttn_overlap": (C.c_int, [P, P, DP]),
             "ttn_export_state": (I64, [P, DP, I64]),
             "ttn_set_graphs": (C.c_int, [P, I32]),
@@ -121,6 +124,7 @@ def make_config(w, keep: list) -> Config:
     cfg.dress_eps = w.dress_eps
     cfg.dress_noise = _dptr(noise) if noise is not None else C.POINTER(C.c_double)()
     cfg.dress_noise_len = 0 if noise is None else noise.size // 2
+    cfg.gamma = float(getattr(w, "gamma", 0.0))
     return cfg
 
 
@@ -153,6 +157,8 @@ class TTN:
         self._check(rc, None)
         self.h = h
         self.set_pulses(w.seg_edges, w.omega, w.delta, w.events)
+        if getattr(w, "omega_x", None) is not None or getattr(w, "omega_z", None) is not None:
+            self.set_qubit_pulses(w.omega_x, w.omega_z)
 
     def _check(self, rc, h):
         if rc < 0:
@@ -170,6 +176,15 @@ class TTN:
         self._pulses = (edges, om, de, steps, sites, us)
         rc = lib().ttn_set_pulses(self.h, int(om.shape[1]) if om.ndim == 2 else 0, _dptr(edges), _dptr(om),
                                   _dptr(de), len(events), _iptr(steps), _iptr(sites), _dptr(us))
+        self._check(rc, self.h)
+
+    def set_qubit_pulses(self, omega_x, omega_z):
+        """Omega^x / Omega^z tables [N][n_seg] on the current segments (None = zero)."""
+        ox = None if omega_x is None else np.ascontiguousarray(omega_x, dtype=np.float64)
+        oz = None if omega_z is None else np.ascontiguousarray(omega_z, dtype=np.float64)
+        self._qubit = (ox, oz)
+        null = C.POINTER(C.c_double)()
+        rc = lib().ttn_set_qubit_pulses(self.h, null if ox is None else _dptr(ox), null if oz is None else _dptr(oz))
         self._check(rc, self.h)
 
     def step(self, n_steps: int, dt: Optional[float] = None, stats: bool = False):
@@ -194,6 +209,12 @@ class TTN:
         n2, e = C.c_double(0), C.c_double(0)
         self._check(lib().ttn_observables(self.h, C.byref(n2), C.byref(e)), self.h)
         return n2.value, e.value
+
+    def rydberg_population(self) -> float:
+        """sum_i <psi|n_i|psi> of the (unnormalised) current state."""
+        p = C.c_double(0)
+        self._check(lib().ttn_rydberg_population(self.h, C.byref(p)), self.h)
+        return p.value
 
     def local_expectation(self, site: int, op) -> complex:
         o = _complex_interleaved(op)

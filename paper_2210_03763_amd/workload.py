@@ -70,6 +70,10 @@ class Workload:
     seed: int
     ckpt_every: int = 0
     gamma: float = 0.0        # Rydberg decay rate of the open-system mode (0: closed system)
+    # single-qubit drive on {|0>, |1>} of Eq. (eq:ham): Omega^x sigma^x + Omega^z sigma^z,
+    # [N, S] on the same segments as omega/delta; None = zero
+    omega_x: Optional[np.ndarray] = None
+    omega_z: Optional[np.ndarray] = None
 
     @property
     def n_sites(self) -> int:
@@ -93,6 +97,17 @@ def square_positions(Lx: int, Ly: int) -> np.ndarray:
     for y in range(Ly):
         for x in range(Lx):
             pos[y * Lx + x] = (x, y)
+    return pos
+
+
+def hex_positions(Lx: int, Ly: int) -> np.ndarray:
+    """Hexagonal (triangular) arrangement with spacing a: site s = y * Lx + x
+    sits at (x + (y mod 2)/2, y sqrt(3)/2), every atom has its nearest
+    neighbours at distance a (Sec. on hexagonal lattices)."""
+    pos = np.zeros((Lx * Ly, 2), dtype=np.float64)
+    for y in range(Ly):
+        for x in range(Lx):
+            pos[y * Lx + x] = (x + 0.5 * (y % 2), y * math.sqrt(3.0) / 2.0)
     return pos
 
 
@@ -220,14 +235,15 @@ def _uniform_pulses(rng, n_sites, n_seg, active=None):
     return om, de
 
 
-def ghz_layers(Lx: int, Ly: int, centre: int, n_layers_max: int, r_g: float):
+def ghz_layers(Lx: int, Ly: int, centre: int, n_layers_max: int, r_g: float, pos=None):
     """Greedy parallel GHZ schedule (a simple stand-in for the paper's
     compiler): layer by layer, disjoint (control in GHZ, target not yet in
-    GHZ) nearest-neighbour pairs, targets ordered by distance to the centre
-    then index; atoms of different pairs in one layer keep a distance >= r_g.
-    Returns the list of layers (each a list of (control, target)) or None if
-    the lattice is not covered within n_layers_max layers."""
-    pos = square_positions(Lx, Ly)
+    GHZ) nearest-neighbour pairs (distance a), targets ordered by distance to
+    the centre then index; atoms of different pairs in one layer keep a
+    distance >= r_g.  Returns the list of layers (each a list of (control,
+    target)) or None if the lattice is not covered within n_layers_max
+    layers.  pos: site positions (default: the square lattice)."""
+    pos = square_positions(Lx, Ly) if pos is None else np.asarray(pos, dtype=np.float64)
     n = Lx * Ly
     cpos = pos[centre]
 
@@ -268,8 +284,16 @@ def ghz_layers(Lx: int, Ly: int, centre: int, n_layers_max: int, r_g: float):
     return layers
 
 
+def hadamard_pulse_amplitude(n_steps: int, dt: float) -> float:
+    """Omega^x = Omega^z = a for n_steps steps of dt gives
+    exp(-i pi/2 (sigma^x + sigma^z)/sqrt 2) = -i H on {|0>, |1>}: a Hadamard
+    as a square pulse of Eq. (eq:ham) (a global phase -i on the qubit
+    levels, none on |r>)."""
+    return math.pi / (2.0 * math.sqrt(2.0) * n_steps * dt)
+
+
 def _layer_program(rng, Lx, Ly, d, n_steps, dt, layers, seg_per_layer, per_site_global=False,
-                   n_global_seg=8):
+                   n_global_seg=8, gates="exact", gate_steps=2, centre=None):
     """Pulse tables + gate events for a layered CZ-type program.
 
     Layer l covers steps [floor(n_steps*l/L), floor(n_steps*(l+1)/L)); its
@@ -277,17 +301,41 @@ def _layer_program(rng, Lx, Ly, d, n_steps, dt, layers, seg_per_layer, per_site_
     at the step after its end.  Inside a layer only its atoms are driven,
     over `seg_per_layer` segments whose edges sit on step boundaries.
     With per_site_global, every site is driven on `n_global_seg` equal
-    global segments instead (the gradient workload)."""
+    global segments instead (the gradient workload).
+
+    gates="pulse": the Hadamards are square sigma^x/sigma^z pulses of
+    gate_steps steps at the start and at the end of the layer window instead
+    (the centre's first Hadamard joins the first window of layer 0), and the
+    CZ-type drive fills the steps between them.  Returns (edges, omega,
+    delta, events, omega_x, omega_z); the last two are None for exact gates."""
     n = Lx * Ly
     L = len(layers)
     had = hadamard_gate(d)
     events = []
     edges = [0.0]
     act = []
+    hwin = []       # per segment: sites carrying a Hadamard pulse
     for l, pairs in enumerate(layers):
         s0 = (n_steps * l) // L
         s1 = (n_steps * (l + 1)) // L
-        for _, t in pairs:
+        targets = {t for _, t in pairs}
+        if gates == "pulse":
+            if s1 - s0 < 2 * gate_steps + seg_per_layer:
+                raise ValueError("layer window too short for its gate pulses")
+            first = targets | ({centre} if (l == 0 and centre is not None) else set())
+            lo, hi = s0 + gate_steps, s1 - gate_steps
+            edges.append(lo * dt)
+            act.append(set())
+            hwin.append(first)
+            for k in range(seg_per_layer):
+                edges.append((lo + ((hi - lo) * (k + 1)) // seg_per_layer) * dt)
+                act.append({a for pr in pairs for a in pr})
+                hwin.append(set())
+            edges.append(s1 * dt)
+            act.append(set())
+            hwin.append(targets)
+            continue
+        for t in targets:
             events.append((s0, t, had.copy()))
             events.append((s1, t, had.copy()))
         if not per_site_global:
@@ -302,7 +350,13 @@ def _layer_program(rng, Lx, Ly, d, n_steps, dt, layers, seg_per_layer, per_site_
         om, de = _uniform_pulses(rng, n, n_global_seg)
     else:
         om, de = _uniform_pulses(rng, n, len(act), act)
-    return np.asarray(edges), om, de, events
+    if gates != "pulse":
+        return np.asarray(edges), om, de, events, None, None
+    a = hadamard_pulse_amplitude(gate_steps, dt)
+    ox = np.zeros((n, len(act)))
+    for k, sites in enumerate(hwin):
+        ox[list(sites), k] = a
+    return np.asarray(edges), om, de, events, ox, ox.copy()
 
 
 # ---------------------------------------------------------------------------
@@ -348,26 +402,35 @@ def make_random_drive(Lx, Ly, d, chi, n_steps, dt, n_seg, seed, plus_sites=(0,),
 
 
 def make_ghz_program(Lx, Ly, d, chi, n_steps, dt, seed, n_layers=14, seg_per_layer=8,
-                     per_site_global=False, eps=1e-2, precision=PREC_FP64, name="ghz"):
+                     per_site_global=False, eps=1e-2, precision=PREC_FP64, name="ghz",
+                     lattice="square", gates="exact", gate_steps=2):
     """GHZ-preparation program: |0...0>, exact Hadamard on the centre atom
     at step 0, then CZ-type layers (Hadamard on targets around seeded
     random drive windows).  The widest inter-gate distance r_G in
     {2, sqrt 2, 1} whose greedy schedule covers the lattice within
-    n_layers layers is used."""
+    n_layers layers is used.  lattice="hex" places the atoms on the
+    hexagonal arrangement (the tree keeps the index Hilbert order);
+    gates="pulse" drives every Hadamard as a sigma^x/sigma^z square pulse of
+    gate_steps steps through the TDVP instead of an exact gate."""
     rng = np.random.Generator(np.random.PCG64(seed))
     kw = _base(name, Lx, Ly, d, chi, n_steps, dt, seed, precision, eps)
+    if lattice == "hex":
+        kw["pos_xy"] = hex_positions(Lx, Ly)
+    elif lattice != "square":
+        raise ValueError(lattice)
     centre = (Ly // 2 - 1) * Lx + (Lx // 2 - 1)
     layers = None
     for r_g in (2.0, math.sqrt(2.0), 1.0):
-        layers = ghz_layers(Lx, Ly, centre, n_layers, r_g)
+        layers = ghz_layers(Lx, Ly, centre, n_layers, r_g, pos=kw["pos_xy"])
         if layers is not None:
             break
     if layers is None:
         raise RuntimeError("no GHZ schedule fits")
-    edges, om, de, ev = _layer_program(rng, Lx, Ly, d, n_steps, dt, layers, seg_per_layer,
-                                       per_site_global)
-    kw.update(seg_edges=edges, omega=om, delta=de)
-    kw["events"] = [(0, centre, hadamard_gate(d))] + ev
+    edges, om, de, ev, ox, oz = _layer_program(rng, Lx, Ly, d, n_steps, dt, layers, seg_per_layer,
+                                               per_site_global, gates=gates, gate_steps=gate_steps,
+                                               centre=centre)
+    kw.update(seg_edges=edges, omega=om, delta=de, omega_x=ox, omega_z=oz)
+    kw["events"] = ([(0, centre, hadamard_gate(d))] if gates != "pulse" else []) + ev
     return _finish(kw, rng)
 
 
@@ -382,7 +445,7 @@ def make_repcode_program(Lx, Ly, d, chi, n_steps, dt, seed, eps=1e-2, precision=
     centre = cy * Lx + cx
     nbrs = [cy * Lx + cx + 1, (cy + 1) * Lx + cx, cy * Lx + cx - 1, (cy - 1) * Lx + cx]
     layers = [[(centre, t)] for t in nbrs]
-    edges, om, de, ev = _layer_program(rng, Lx, Ly, d, n_steps, dt, layers, seg_per_layer)
+    edges, om, de, ev, _, _ = _layer_program(rng, Lx, Ly, d, n_steps, dt, layers, seg_per_layer)
     kw.update(seg_edges=edges, omega=om, delta=de)
     kw["events"] = [(0, centre, hadamard_gate(d))] + ev
     kw["target_sites"] = np.asarray([centre] + nbrs, dtype=np.int32)
@@ -408,6 +471,10 @@ def config(name: str, **over) -> Workload:
         w = make_ghz_program(8, 8, 3, 64, 200, 0.005, seed0 + 4, per_site_global=True,
                              name="8x8 d3 chi64 GHZ gates, 64x8 per-site segments")
         w.ckpt_every = 10
+    elif name == "hex-pulse":   # 8x8 hexagonal, Hadamards as sigma^x/sigma^z square pulses
+        w = make_ghz_program(8, 8, 4, 128, 200, 0.005, seed0 + 6, precision=PREC_FP32, lattice="hex",
+                             gates="pulse", gate_steps=2,
+                             name="8x8 hexagonal d4 chi128 GHZ program, pulse-driven gates (mixed)")
     elif name == "c5":
         w = make_repcode_program(8, 8, 4, 256, 400, 0.0025, seed0 + 5, precision=PREC_FP32,
                                  name="8x8 d4 chi256 repetition code (mixed)")

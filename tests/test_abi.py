@@ -42,7 +42,7 @@ def test_workspace_query_sizes():
 
 
 @pytest.mark.parametrize("field,value", [("n_sites", 12), ("d", 5), ("chi", 0), ("krylov_dim", 17),
-                                         ("precision", 7)])
+                                         ("precision", 7), ("gamma", -0.1), ("gamma", float("nan"))])
 def test_invalid_config_rejected(field, value):
     w = W.config("c1-ent")
     keep = []
@@ -66,6 +66,8 @@ def test_null_handle_calls():
     assert L.ttn_destroy(None) == T.TTN_EINVAL
     assert L.ttn_backward(None, 0, None, 1.0, None, None) == T.TTN_EINVAL
     assert L.ttn_record_begin(None, 1, 1, None, 0) == T.TTN_EINVAL
+    assert L.ttn_rydberg_population(None, None) == T.TTN_EINVAL
+    assert L.ttn_set_qubit_pulses(None, None, None) == T.TTN_EINVAL
 
 
 def _validate(w, n_steps=1):
@@ -91,6 +93,13 @@ def _validate(w, n_steps=1):
     ("8x8 d4 chi128 fp32", lambda: W.make_ghz_program(8, 8, 4, 128, 1, 0.005, seed=1, eps=0.0,
                                                      precision=1)),
     ("8x8 d4 chi128 fp64", lambda: W.make_ghz_program(8, 8, 4, 128, 1, 0.005, seed=1, eps=0.0)),
+    ("2x1 d3 chi9 open", lambda: W.make_random_drive(2, 1, 3, 9, 1, 0.01, 1, seed=1).copy(gamma=0.1)),
+    ("4x4 d4 chi12 fp32 open", lambda: W.make_random_drive(4, 4, 4, 12, 1, 0.01, 1, seed=1,
+                                                           precision=1).copy(gamma=0.1)),
+    ("2x4 hex d3 chi8 pulse gates", lambda: W.make_ghz_program(4, 2, 3, 8, 40, 0.02, 5, n_layers=4, seg_per_layer=2,
+                                                               lattice="hex", gates="pulse")),
+    ("8x8 d4 chi128 fp32 open", lambda: W.make_ghz_program(8, 8, 4, 128, 1, 0.005, seed=1, eps=0.0,
+                                                          precision=1).copy(gamma=0.02)),
 ])
 def test_launch_plan_stays_in_bounds(case):
     """Every GEMM operand and vector launch of init + steps + observables stays
