@@ -679,8 +679,10 @@ void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
     if (o.Wb) convert_d2f(o.Wb, h->Wf, 2 * (1 + o.sL + o.sR) * P2, skip, h->stream);
 }
 
+// staged: the mixed-precision matvec whose input is already in the FP32 slot
+// (h->Xf) and whose output stays in h->Yf (the Lanczos kernels convert)
 void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, const int* skip,
-                   bool force_fp64 = false) {
+                   bool force_fp64 = false, bool staged = false) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
     struct HeffMark {
         ttn_handle* h;
@@ -692,10 +694,10 @@ void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, c
     } mark(h);
     if (h->prec == TTN_PREC_FP32 && !force_fp64) {
         Ctx<float> c{h, skip};
-        convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
+        if (!staged) convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
         apply_op<float>(c, o, h->Lf, o.Rb ? h->Rf : nullptr, o.Bb ? h->Bf : nullptr,
                         o.Wb ? h->Wf : nullptr, h->Xf, h->Yf);
-        convert_f2d(h->Yf, y, 2 * n, skip, h->stream);
+        if (!staged) convert_f2d(h->Yf, y, 2 * n, skip, h->stream);
     } else {
         Ctx<double> c{h, skip};
         copy_d(x, h->X, 2 * n, skip, h->stream);
@@ -720,7 +722,10 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
         chk(h, h->Yf, n, "fp32 output");
         stage_f32(h, o, nullptr);
     }
-    lz_start(x, n, h->Vk, lz, h->red, nb, s, h->nonherm ? 1 : 0);
+    // mixed precision: the Lanczos kernels write the FP32 input of the next
+    // matvec and widen its FP32 output themselves
+    float* xf = (h->prec == TTN_PREC_FP32 && n > LZ_SMALL_N) ? h->Xf : nullptr;
+    lz_start(x, n, h->Vk, lz, h->red, nb, s, h->nonherm ? 1 : 0, xf);
     if (n <= LZ_SMALL_N) {
         for (int j = 0; j < h->m; ++j) {
             apply_op_prec(h, o, h->Vk + 2 * n * j, h->W, &lz->done);
@@ -730,12 +735,12 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     }
     for (int j = 0; j < h->m; ++j) {
         double* vj = h->Vk + 2 * n * j;
-        apply_op_prec(h, o, vj, h->W, &lz->done);
+        apply_op_prec(h, o, vj, h->W, &lz->done, false, xf != nullptr);
         // classical Gram-Schmidt, two passes: the first projection also gives alpha_j
-        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s);
+        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s, xf ? h->Yf : nullptr);
         if (j == h->m - 1) break;
         lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s);
-        lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s);
+        lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s, xf);
     }
 }
 

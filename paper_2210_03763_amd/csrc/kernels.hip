@@ -105,18 +105,24 @@ __global__ void k_lz_begin(const double* partial, int nb, LanczosDev* lz, int no
     }
 }
 
+// y = x / beta (FP64), and its FP32 copy yf when yf != nullptr (the input of
+// the next mixed-precision matvec)
 __global__ void k_scale_by(const double* x, int64_t n, double* y, const LanczosDev* lz, int use_beta0,
-                           int j) {
+                           int j, float* yf) {
     if (lz->done) return;
     const double s = 1.0 / (use_beta0 ? lz->beta0 : lz->beta[j]);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = x[i] * s;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = x[i] * s;
+        y[i] = v;
+        if (yf) yf[i] = (float)v;
+    }
 }
 
-// partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < kcount
+// partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < kcount; with wf != nullptr
+// w is first widened from the FP32 matvec output wf (and stored)
 __global__ __launch_bounds__(256) void k_multidot_partial(const double* V, int kcount, const double* w, int64_t n,
-                                                         double* partial, const LanczosDev* lz) {
+                                                         double* partial, const LanczosDev* lz, const float* wf) {
     if (lz->done) return;
     __shared__ double sh32[4 * 32];
     double re[KRYLOV_MAX], im[KRYLOV_MAX];
@@ -131,7 +137,16 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* V, int k
                 vi[k] = V[2 * n * k + n + i];
             }
         }
-        const double wr = w[i], wi = w[i + n];
+        double wr, wi;
+        if (wf) {
+            wr = (double)wf[i];
+            wi = (double)wf[i + n];
+            const_cast<double*>(w)[i] = wr;
+            const_cast<double*>(w)[i + n] = wi;
+        } else {
+            wr = w[i];
+            wi = w[i + n];
+        }
 #pragma unroll
         for (int k = 0; k < KRYLOV_MAX; ++k) {
             if (k < kcount) {
@@ -561,6 +576,7 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
         double ar = 0, ai = 0;
         if (k < sL) {
             const double* op = L + 2 * L2 * (k + 1);
+#pragma unroll 4
             for (int q = 0; q < DL; ++q) {
                 const double orr = op[l + DL * q], oi = op[L2 + l + DL * q];
                 const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
@@ -569,6 +585,7 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
             }
         } else {
             const double* op = Rr + 2 * R2 * (k - sL + 1);
+#pragma unroll 4
             for (int q = 0; q < DR; ++q) {
                 const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
                 const double xr = x[l + DL * (q + DR * p)], xi = x[n + l + DL * (q + DR * p)];
@@ -583,6 +600,7 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int l = i % DL, r = (i / DL) % DR, p = i / (DL * DR);
         double ar = 0, ai = 0;
+#pragma unroll 4
         for (int q = 0; q < DL; ++q) {   // block Hamiltonian of the left leg
             const double orr = L[l + DL * q], oi = L[L2 + l + DL * q];
             const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
@@ -593,7 +611,8 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
             for (int k = 0; k <= sL; ++k) {   // right leg: H_R x + sum_i A_i U_i
                 const double* op = B + 2 * R2 * k;
                 const double* src = k == 0 ? x : S + 2 * n * (k - 1);
-                for (int q = 0; q < DR; ++q) {
+    #pragma unroll 4
+            for (int q = 0; q < DR; ++q) {
                     const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
                     const double xr = src[l + DL * (q + DR * p)], xi = src[n + l + DL * (q + DR * p)];
                     ar += orr * xr - oi * xi;
@@ -604,6 +623,7 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
             for (int k = 0; k <= sL + nz; ++k) {   // parent leg: H_P x + sum W U + sum W Z
                 const double* op = W + 2 * P2 * k;
                 const double* src = k == 0 ? x : S + 2 * n * (k - 1);
+#pragma unroll 4
                 for (int q = 0; q < DP; ++q) {
                     const double orr = op[p + DP * q], oi = op[P2 + p + DP * q];
                     const double xr = src[l + DL * (r + DR * q)], xi = src[n + l + DL * (r + DR * q)];
@@ -797,19 +817,19 @@ void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_
 }
 
 void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
-              hipStream_t s, int nonherm) {
+              hipStream_t s, int nonherm, float* v0f) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, x, n, partial,
                        (const int*)nullptr);
     hipLaunchKernelGGL(k_lz_begin, dim3(1), dim3(64), 0, s, partial, nb, lz, nonherm);
-    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, x, n, v0, lz, 1, 0);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, x, n, v0, lz, 1, 0, v0f);
 }
 
 void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
-                LanczosDev* lz, int alpha_index, hipStream_t s) {
+                LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_multidot_partial, dim3(nb), dim3(RED_THREADS), 0, s, V, kcount, w, n,
-                       partial, lz);
+                       partial, lz, wf);
     hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64 * kcount), 0, s, partial, nb, kcount, lz,
                        alpha_index);
 }
@@ -827,11 +847,11 @@ void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, doub
 }
 
 void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
-                      double* partial, int nb, double tol, hipStream_t s) {
+                      double* partial, int nb, double tol, hipStream_t s, float* vnextf) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_sub_fused<2>, dim3(nb), dim3(256), 0, s, V, kcount, w, n, partial, lz);
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s, partial, nb, lz, j, tol);
-    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j, vnextf);
 }
 
 void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
@@ -839,7 +859,8 @@ void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double*
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, w, n, partial, &lz->done);
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s, partial, nb, lz, j, tol);
-    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j,
+                       (float*)nullptr);
 }
 
 void lz_iter_small(double* V, int j, int m, double* w, int64_t n, LanczosDev* lz, double tol, hipStream_t s) {

@@ -89,17 +89,19 @@ void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_
 // nonherm != 0 starts an Arnoldi basis (non-Hermitian operator): the
 // projections of both Gram-Schmidt passes are kept as Hessenberg columns and
 // lz_expm exponentiates the Hessenberg matrix instead of the tridiagonal one
+// v0f != nullptr also receives v0 in FP32 (the next mixed matvec's input)
 void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
-              hipStream_t s, int nonherm = 0);
+              hipStream_t s, int nonherm = 0, float* v0f = nullptr);
+// wf != nullptr: w is first written from the FP32 matvec output wf (widened)
 void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
-                LanczosDev* lz, int alpha_index, hipStream_t s);
+                LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf = nullptr);
 void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s);
 // w -= V c, then c <- V^H w (second Gram-Schmidt pass), fused
 void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, double* partial, int nb,
                          LanczosDev* lz, hipStream_t s);
 // w -= V c, then beta_j = ||w||, breakdown test, v_{j+1} = w / beta_j
 void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
-                      double* partial, int nb, double tol, hipStream_t s);
+                      double* partial, int nb, double tol, hipStream_t s, float* vnextf = nullptr);
 void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
              double tol, hipStream_t s);
 // a whole iteration after the matvec (projection, two Gram-Schmidt passes,
