@@ -238,8 +238,14 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, 
     constexpr int QA = BM * BK / NT, QB = BN * BK / NT;
     static_assert(QA >= 1 && QB >= 1, "tile smaller than the block");
     typedef typename MfmaT<R>::acc_t acc_t;
-    __shared__ R As[2][2][BK][BM + PAD];
-    __shared__ R Bs[2][2][BK][BN + PAD];
+    // LDS tiles [buffer][plane][row][col]: an operand whose global layout is
+    // contiguous along k is staged k-contiguous with an odd row stride
+    // (BK + 1), so that both the coalesced stash and the MFMA fragment reads
+    // hit distinct banks; the others are staged [k][index] with a pad.
+    constexpr int AR = AK ? BM : BK, AC = AK ? BK + 1 : BM + PAD;
+    constexpr int BR = BKF ? BN : BK, BC = BKF ? BK + 1 : BN + PAD;
+    __shared__ R As[2][2][AR][AC];
+    __shared__ R Bs[2][2][BR][BC];
     int64_t bid = blockIdx.x;
     const int tm = bid % tilesM;
     bid /= tilesM;
@@ -299,15 +305,15 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, 
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q;
             const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
-            As[buf][0][kk][mm] = pa[0][q];
-            As[buf][1][kk][mm] = pa[1][q];
+            As[buf][0][AK ? mm : kk][AK ? kk : mm] = pa[0][q];
+            As[buf][1][AK ? mm : kk][AK ? kk : mm] = pa[1][q];
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             const int e = tid + NT * q;
             const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
-            Bs[buf][0][kk][nn] = pb[0][q];
-            Bs[buf][1][kk][nn] = pb[1][q];
+            Bs[buf][0][BKF ? nn : kk][BKF ? kk : nn] = pb[0][q];
+            Bs[buf][1][BKF ? nn : kk][BKF ? kk : nn] = pb[1][q];
         }
     };
     acc_t c1[TI][TJ], c2[TI][TJ], c3[TI][TJ];
@@ -334,14 +340,16 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, 
             R br[TJ], bi[TJ], bs[TJ], ar[TI], ai[TI], as[TI];
 #pragma unroll
             for (int j = 0; j < TJ; ++j) {
-                br[j] = Bs[cur][0][kr][wn0 + 16 * j + c16];
-                bi[j] = Bs[cur][1][kr][wn0 + 16 * j + c16];
+                const int bn = wn0 + 16 * j + c16;
+                br[j] = BKF ? Bs[cur][0][bn][kr] : Bs[cur][0][kr][bn];
+                bi[j] = BKF ? Bs[cur][1][bn][kr] : Bs[cur][1][kr][bn];
                 bs[j] = br[j] + bi[j];
             }
 #pragma unroll
             for (int i = 0; i < TI; ++i) {
-                ar[i] = As[cur][0][kr][wm0 + 16 * i + c16];
-                ai[i] = As[cur][1][kr][wm0 + 16 * i + c16];
+                const int am = wm0 + 16 * i + c16;
+                ar[i] = AK ? As[cur][0][am][kr] : As[cur][0][kr][am];
+                ai[i] = AK ? As[cur][1][am][kr] : As[cur][1][kr][am];
                 as[i] = ar[i] + ai[i];
             }
             // the three products of one tile are independent: back-to-back
@@ -460,8 +468,11 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
         int splits = 1;
         const int ktiles = K / 16;
+        // split K until the grid covers the chip once: 256 workgroups of the
+        // large tiles (one resident per CU), 512 of the small ones (two per CU)
+        const int64_t target = big ? 256 : 512;
         if (tiles < 256 && ktiles >= 8) {
-            splits = (int)std::min<int64_t>((512 + tiles - 1) / tiles, ktiles / 4);
+            splits = (int)std::min<int64_t>((target + tiles - 1) / tiles, ktiles / 4);
             const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
             const int64_t cap = per > 0 ? ws.bytes / per : 1;
             if (splits > cap) splits = (int)cap;

@@ -380,23 +380,31 @@ __global__ void k_lz_beta(const double* partial, int nb, LanczosDev* lz, int j, 
     }
 }
 
-// y = exp(-i tau T) e_1 for the real symmetric tridiagonal T (alpha, beta)
-// of size m_eff: the Taylor series of exp(B/s), B = -i tau T, applied s times
-// to the vector, with s chosen so that ||B/s||_1 <= 1/4 (terms are summed
-// until they stop changing the result in double precision).
-// y = exp(-i tau H) e_1 for the complex upper Hessenberg H of an Arnoldi
-// basis (columns in hs, subdiagonal beta) of size m_eff: the same scaled
-// Taylor series, one thread per row of H for the products H term.
+// y = exp(-i tau H) e_1 for the m_eff x m_eff projection H of the Krylov
+// basis: the Taylor series of exp(B/s), B = -i tau H, applied s times to the
+// vector, with s chosen so that ||B/s||_1 <= 1/4 (terms are summed until they
+// stop changing the result in double precision); one thread per row of H for
+// the products H term.  H is the real symmetric tridiagonal (alpha, beta) of
+// a Lanczos basis, or the complex upper Hessenberg matrix of an Arnoldi
+// basis (columns in hs, subdiagonal beta) when lz->nonherm.
 __device__ void lz_expm_hessenberg(LanczosDev* lz, double tau, StepDev* st) {
     constexpr int KM = KRYLOV_MAX;
     __shared__ double Hr[KM][KM + 1], Hi[KM][KM + 1];
     __shared__ double tr[KM], ti[KM], wr[KM], wi[KM], vr[KM], vi[KM];
     const int m = lz->m_eff, t = threadIdx.x;
+    const bool herm = !lz->nonherm;
     for (int e = t; e < KM * KM; e += blockDim.x) {
         const int row = e % KM, col = e / KM;
         double a = 0.0, b = 0.0;
         if (row < m && col < m) {
-            if (row <= col) {
+            if (herm) {
+                if (row == col)
+                    a = lz->alpha[col];
+                else if (row == col + 1)
+                    a = lz->beta[col];
+                else if (col == row + 1)
+                    a = lz->beta[row];
+            } else if (row <= col) {
                 a = lz->hs[2 * (col * KM + row)];
                 b = lz->hs[2 * (col * KM + row) + 1];
             } else if (row == col + 1) {
@@ -466,90 +474,9 @@ __device__ void lz_expm_hessenberg(LanczosDev* lz, double tau, StepDev* st) {
     if (t == 0) atomicMin(&st->min_krylov, m);
 }
 
-// The tridiagonal case (one thread).
-__device__ void lz_expm_tridiag(LanczosDev* lz, double tau, StepDev* st) {
-    const int m = lz->m_eff;
-    double al[KRYLOV_MAX], be[KRYLOV_MAX];
-#pragma unroll
-    for (int i = 0; i < KRYLOV_MAX; ++i) {
-        al[i] = i < m ? lz->alpha[i] : 0.0;
-        be[i] = i + 1 < m ? lz->beta[i] : 0.0;   // T[i][i+1] = T[i+1][i] = beta[i]
-    }
-    double nrm = 0;
-#pragma unroll
-    for (int i = 0; i < KRYLOV_MAX; ++i) {
-        const double c = fabs(al[i]) + fabs(be[i]) + (i > 0 ? fabs(be[i - 1]) : 0.0);
-        nrm = c > nrm ? c : nrm;
-    }
-    nrm *= fabs(tau);
-    int ns = (int)ceil(nrm / 0.25);
-    if (ns < 1) ns = 1;
-    const double h = tau / ns;
-    double vr[KRYLOV_MAX], vi[KRYLOV_MAX];
-#pragma unroll
-    for (int i = 0; i < KRYLOV_MAX; ++i) {
-        vr[i] = i == 0 ? 1.0 : 0.0;
-        vi[i] = 0.0;
-    }
-    for (int rep = 0; rep < ns; ++rep) {
-        double tr[KRYLOV_MAX], ti[KRYLOV_MAX], wr[KRYLOV_MAX], wi[KRYLOV_MAX];
-#pragma unroll
-        for (int i = 0; i < KRYLOV_MAX; ++i) {
-            tr[i] = wr[i] = vr[i];
-            ti[i] = wi[i] = vi[i];
-        }
-        for (int k = 1; k <= 40; ++k) {
-            // term <- (-i h T term) / k :  re' = h (T ti) / k,  im' = -h (T tr) / k
-            double nr[KRYLOV_MAX], ni[KRYLOV_MAX];
-            const double f = h / k;
-            double tmax = 0, wmax = 0;
-#pragma unroll
-            for (int i = 0; i < KRYLOV_MAX; ++i) {
-                double sr = al[i] * tr[i], si = al[i] * ti[i];
-                if (i > 0) {
-                    sr += be[i - 1] * tr[i - 1];
-                    si += be[i - 1] * ti[i - 1];
-                }
-                if (i + 1 < KRYLOV_MAX) {
-                    sr += be[i] * tr[i + 1];
-                    si += be[i] * ti[i + 1];
-                }
-                nr[i] = f * si;
-                ni[i] = -f * sr;
-            }
-#pragma unroll
-            for (int i = 0; i < KRYLOV_MAX; ++i) {
-                tr[i] = nr[i];
-                ti[i] = ni[i];
-                wr[i] += tr[i];
-                wi[i] += ti[i];
-                const double ta = fabs(tr[i]) + fabs(ti[i]), wa = fabs(wr[i]) + fabs(wi[i]);
-                tmax = ta > tmax ? ta : tmax;
-                wmax = wa > wmax ? wa : wmax;
-            }
-            if (tmax <= 1e-18 * wmax) break;
-        }
-#pragma unroll
-        for (int i = 0; i < KRYLOV_MAX; ++i) {
-            vr[i] = wr[i];
-            vi[i] = wi[i];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < KRYLOV_MAX; ++i) {
-        lz->y[2 * i] = i < m ? vr[i] : 0.0;
-        lz->y[2 * i + 1] = i < m ? vi[i] : 0.0;
-    }
-    atomicMin(&st->min_krylov, m);
-}
-
 __global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
     if (lz->zero) return;
-    if (lz->nonherm) {
-        lz_expm_hessenberg(lz, tau, st);
-        return;
-    }
-    if (threadIdx.x == 0) lz_expm_tridiag(lz, tau, st);
+    lz_expm_hessenberg(lz, tau, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -762,11 +689,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
         __syncthreads();
     }
     // y = exp(-i tau H_m) e_1, then x = beta0 sum_k y_k v_k
-    if (nonherm) {
-        lz_expm_hessenberg(&lz, tau, st);
-    } else if (threadIdx.x == 0) {
-        lz_expm_tridiag(&lz, tau, st);
-    }
+    lz_expm_hessenberg(&lz, tau, st);
     __syncthreads();
     const int me = lz.m_eff;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {

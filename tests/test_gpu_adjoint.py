@@ -129,3 +129,34 @@ def test_adjoint_8x8_chi64_against_central_differences():
             fd = (Fs[0] - Fs[1]) / (2 * h)
             _say(f"[adjoint] site {i}: adjoint {grad[i, seg]:.10e} fd {fd:.10e}")
             assert abs(fd - grad[i, seg]) <= 1e-6 * scale
+
+
+def test_mixed_precision_adjoint_matches_oracle_4x4():
+    # mixed mode: the taped re-run and the environment-adjoint contractions run
+    # in complex FP32; the gradient must stay within the mixed tolerance
+    w = W.make_ghz_program(4, 4, 3, 12, 12, 0.1, seed=33, n_layers=6, seg_per_layer=2, eps=0.05,
+                           precision=T.PREC_FP32)
+    _say("[adjoint] 4x4 d3 chi12 mixed")
+    F, _, go, gd = _gpu_grad(w, ckpt_every=3)
+    Fo, ro, rd = O.fidelity_gradient(w.copy(precision=T.PREC_FP64))
+    assert abs(F - Fo) < 1e-5
+    _compare(w, go, gd, ro, rd, tol=1e-5)
+
+
+def test_mixed_precision_adjoint_matches_fp64_8x8_chi64():
+    w = W.config("c4").copy(n_steps=4, precision=T.PREC_FP32)
+    bright = sorted({s for (k, s, _) in w.events if k == 0})
+    res = {}
+    for prec in (T.PREC_FP32, T.PREC_FP64):
+        g = T.TTN(w.copy(precision=prec))
+        g.record(w.n_steps, 2)
+        g.step(w.n_steps)
+        F, _ = g.fidelity(bright)
+        res[prec] = (F,) + g.backward(bright)
+        g.close()
+    (Fm, gom, gdm), (F64, go64, gd64) = res[T.PREC_FP32], res[T.PREC_FP64]
+    scale = max(np.abs(go64).max(), np.abs(gd64).max())
+    err = max(np.abs(gom - go64).max(), np.abs(gdm - gd64).max())
+    _say(f"[adjoint] 8x8 chi64 mixed vs FP64: |dF| {abs(Fm - F64):.2e}, max|g| {scale:.3e}, err {err:.3e}")
+    assert scale > 1e-6
+    assert abs(Fm - F64) < 1e-5 and err <= 1e-5 * scale
