@@ -11,6 +11,12 @@ program; inputs are synthetic and seeded and already resident on the device
 when the timed region starts.  The timed steps replay the captured step
 graph; the contraction-kernel timings come from the same number of steps
 right after them, launched eagerly inside a profiling window.
+
+Beside the headline line's fields the JSON carries: fp64_path (the FP64
+path over the same steps and its distance to the mixed result),
+forward_adjoint (recorded steps and the backward pass of the fidelity
+gradient, mixed and FP64), open_system (the same workload with Rydberg
+decay), sampling (10^6 projective-measurement shots) and cpu_baseline.
 """
 from __future__ import annotations
 
@@ -209,6 +215,40 @@ def run_adjoint(w, steps):
             "max_abs_grad": float(max(abs(go).max(), abs(gd).max()))}
 
 
+def run_contract_stage(stage, reps=5, chi=128):
+    """One H_eff stage of a 128^3 node as a single contraction launch through
+    ttn_leg_contract (complex FP32), for kernel-level profiling: A = the left
+    block and 16 left-site operators on a shared tensor, B = 16 right-site
+    operators, C = the right-leg sum over 17 operator/tensor pairs, D = the
+    parent-leg sum over 33 pairs."""
+    import torch
+    from paper_2210_03763_amd import ttn
+    L = ttn.lib()
+    L.ttn_leg_contract.restype = C.c_int
+    L.ttn_leg_contract.argtypes = [C.c_int32] * 6 + [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                                     C.c_int32, C.c_void_p]
+    leg, K, xpo, sm = {"A": (0, 17, 0, 0), "B": (1, 16, 0, 0), "C": (1, 17, 1, 1), "D": (2, 33, 1, 1)}[stage]
+    n = chi ** 3
+    g = torch.Generator(device="cuda").manual_seed(7)
+    ops = torch.randn(K, 2 * chi * chi, dtype=torch.float32, device="cuda", generator=g)
+    x = torch.randn(K if xpo else 1, 2 * n, dtype=torch.float32, device="cuda", generator=g)
+    y = torch.zeros(1 if sm else K, 2 * n, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rc = L.ttn_leg_contract(1, leg, chi, chi, chi, K, ops.data_ptr(), x.data_ptr(), xpo, y.data_ptr(), sm, 0, st)
+        e1.record()
+        torch.cuda.synchronize()
+        assert rc == 0
+        times.append(e0.elapsed_time(e1))
+    ms = min(times[1:]) if reps > 1 else times[0]
+    fl = 8.0 * n * chi * K
+    return {"contract_stage": stage, "shape": f"{chi}^3, {K} operators, leg {leg}", "ms": round(ms, 4),
+            "tflops_algorithmic": round(fl / ms / 1e9, 2), "reps": reps}
+
+
 def run_open(w, steps, warmup, gamma):
     """Open-system mode (Eq. (eq:hoqs): -i gamma |r><r| per site, Arnoldi
     local exponentials) on the same workload: timed steps from the step
@@ -293,6 +333,8 @@ def main():
                     help="launch every step eagerly (for counter collection; kernels are the same)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--contract-stage", choices=["A", "B", "C", "D"], default=None,
+                    help="time one H_eff contraction stage of a 128^3 node instead (kernel profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the TDVP sweep is sequential "
@@ -303,6 +345,9 @@ def main():
     from paper_2210_03763_amd import ttn, workload as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.contract_stage:
+        print(json.dumps(run_contract_stage(args.contract_stage)), flush=True)
+        return
     print(f"[bench] building workload {args.config}", file=sys.stderr, flush=True)
     w = W.config(args.config)
     fps = heff_flops_per_step(w)
