@@ -249,6 +249,67 @@ def run_contract_stage(stage, reps=5, chi=128):
             "tflops_algorithmic": round(fl / ms / 1e9, 2), "reps": reps}
 
 
+def run_c5(steps):
+    """The 8x8, d = 4, chi = 256 repetition-code program: mixed and FP64
+    forward steps/s (one warm-up step each), their distance, and forward +
+    adjoint over `steps` recorded steps (checkpoint every 2) with the mixed
+    gradient's distance to the FP64 one."""
+    import numpy as np
+    import torch
+    from paper_2210_03763_amd import ttn, workload as W
+    w = W.config("c5")
+    out = {"workload": w.name, "steps": steps}
+    fw = {}
+    for prec, key in ((ttn.PREC_FP32, "mixed"), (ttn.PREC_FP64, "fp64")):
+        g = ttn.TTN(w.copy(precision=prec), device="cuda:0")
+        g.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        F, _ = g.fidelity()
+        fw[key] = g
+        out[f"{key}_ms_per_step"] = round(ms, 1)
+        out[f"{key}_F"] = F
+        print(f"[bench] c5 {key}: {ms:.0f} ms/step", file=sys.stderr, flush=True)
+    ov = fw["mixed"].overlap(fw["fp64"])
+    out["abs_dF"] = abs(out["mixed_F"] - out["fp64_F"])
+    out["state_infidelity_C"] = 1 - abs(ov) ** 2
+    out["mixed_speedup"] = round(out["fp64_ms_per_step"] / out["mixed_ms_per_step"], 3)
+    for g in fw.values():
+        g.close()
+    del fw
+    torch.cuda.empty_cache()
+    grads = {}
+    for prec, key in ((ttn.PREC_FP32, "mixed"), (ttn.PREC_FP64, "fp64")):
+        g = ttn.TTN(w.copy(precision=prec), device="cuda:0")
+        g.step(1)
+        nbytes = g.record(steps, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        go, gd = g.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        grads[key] = (go, gd)
+        out[f"{key}_fwd_adj_ms_per_step"] = round((t2 - t0) * 1e3 / steps, 1)
+        out[f"{key}_bwd_ms_per_step"] = round((t2 - t1) * 1e3 / steps, 1)
+        out[f"{key}_adjoint_buffer_gib"] = round(nbytes / 2 ** 30, 2)
+        print(f"[bench] c5 {key} forward+adjoint done", file=sys.stderr, flush=True)
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    scale = max(np.abs(grads["fp64"][0]).max(), np.abs(grads["fp64"][1]).max())
+    err = max(np.abs(grads["mixed"][0] - grads["fp64"][0]).max(), np.abs(grads["mixed"][1] - grads["fp64"][1]).max())
+    out["max_abs_grad_fp64"] = scale
+    out["max_abs_grad_diff"] = err
+    out["mixed_speedup_fwd_adj"] = round(out["fp64_fwd_adj_ms_per_step"] / out["mixed_fwd_adj_ms_per_step"], 3)
+    return out
+
+
 def run_open(w, steps, warmup, gamma):
     """Open-system mode (Eq. (eq:hoqs): -i gamma |r><r| per site, Arnoldi
     local exponentials) on the same workload: timed steps from the step
@@ -333,6 +394,8 @@ def main():
                     help="launch every step eagerly (for counter collection; kernels are the same)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--c5-steps", type=int, default=0,
+                    help="also measure the 8x8 d=4 chi=256 repetition-code program over this many steps")
     ap.add_argument("--contract-stage", choices=["A", "B", "C", "D"], default=None,
                     help="time one H_eff contraction stage of a 128^3 node instead (kernel profiling)")
     args = ap.parse_args()
@@ -408,6 +471,9 @@ def main():
         print(f"[bench] open system: gamma {args.open_gamma}, {args.steps} steps", file=sys.stderr, flush=True)
         out["open_system"] = run_open(w, args.steps, args.warmup, args.open_gamma)
         out["open_system"]["closed_ms_per_step"] = round(ms_mixed, 3)
+    if args.c5_steps > 0:
+        print(f"[bench] chi=256 repetition code: {args.c5_steps} steps", file=sys.stderr, flush=True)
+        out["chi256_repetition_code"] = run_c5(args.c5_steps)
     if args.sample_shots > 0:
         print(f"[bench] sampling: {args.sample_shots} shots", file=sys.stderr, flush=True)
         out["sampling"] = run_sampling(w, args.sample_shots)

@@ -283,3 +283,54 @@ class TTN:
             self.close()
         except Exception:
             pass
+
+
+_FIDELITY_FN = None
+
+
+def _fidelity_function():
+    global _FIDELITY_FN
+    if _FIDELITY_FN is not None:
+        return _FIDELITY_FN
+    import torch
+
+    class TTNFidelity(torch.autograd.Function):
+        """F = |<GHZ_S|psi_n>|^2 after n TDVP steps of a workload whose pulse
+        table is given as tensors, differentiable with respect to that table
+        through the library's adjoint (ttn_record_begin + ttn_backward).
+
+        forward(omega, delta, w, n_steps=None, ckpt_every=10, target_sites=None):
+        omega, delta are [N][n_seg] float64 tensors (any device; copied to the
+        host for ttn_set_pulses); returns F as a 0-d float64 tensor on omega's
+        device.  backward returns dF * dF/dOmega and dF * dF/dDelta."""
+
+        @staticmethod
+        def forward(ctx, omega, delta, w, n_steps=None, ckpt_every=10, target_sites=None):
+            om = omega.detach().to("cpu", torch.float64).numpy()
+            de = delta.detach().to("cpu", torch.float64).numpy()
+            n = w.n_steps if n_steps is None else int(n_steps)
+            g = TTN(w.copy(omega=om, delta=de))
+            g.record(n, ckpt_every)
+            g.step(n)
+            F, _ = g.fidelity(target_sites)
+            ctx.g = g
+            ctx.target = target_sites
+            ctx.dev = omega.device
+            return torch.tensor(F, dtype=torch.float64, device=omega.device)
+
+        @staticmethod
+        def backward(ctx, gF):
+            go, gd = ctx.g.backward(ctx.target, float(gF))
+            ctx.g.close()
+            ctx.g = None
+            return (torch.as_tensor(go, device=ctx.dev), torch.as_tensor(gd, device=ctx.dev), None, None, None,
+                    None)
+
+    _FIDELITY_FN = TTNFidelity
+    return TTNFidelity
+
+
+def ttn_fidelity(omega, delta, w, n_steps=None, ckpt_every=10, target_sites=None):
+    """Differentiable GHZ fidelity of workload w under the pulse tensors
+    (omega, delta): see TTNFidelity."""
+    return _fidelity_function().apply(omega, delta, w, n_steps, ckpt_every, target_sites)

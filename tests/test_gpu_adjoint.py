@@ -160,3 +160,18 @@ def test_mixed_precision_adjoint_matches_fp64_8x8_chi64():
     _say(f"[adjoint] 8x8 chi64 mixed vs FP64: |dF| {abs(Fm - F64):.2e}, max|g| {scale:.3e}, err {err:.3e}")
     assert scale > 1e-6
     assert abs(Fm - F64) < 1e-5 and err <= 1e-5 * scale
+
+
+def test_autograd_function_matches_oracle_gradient():
+    # the torch.autograd.Function front end: F(Omega, Delta) on tensors, an
+    # upstream factor of 2 through a loss, against the oracle's gradient
+    import torch
+    w = W.make_ghz_program(4, 2, 3, 6, 16, 0.1, seed=31, n_layers=4, seg_per_layer=2, eps=0.05)
+    om = torch.tensor(w.omega, dtype=torch.float64, device="cuda", requires_grad=True)
+    de = torch.tensor(w.delta, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = T.ttn_fidelity(om, de, w, ckpt_every=4)
+    (2.0 * F).backward()
+    Fo, ro, rd = O.fidelity_gradient(w)
+    _say(f"[adjoint] autograd: F {float(F):.12f} vs {Fo:.12f}")
+    assert abs(float(F) - Fo) < 1e-10
+    _compare(w, om.grad.cpu().numpy(), de.grad.cpu().numpy(), 2 * ro, 2 * rd)
