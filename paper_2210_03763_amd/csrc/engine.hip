@@ -744,13 +744,25 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     }
 }
 
+// Whether an operator of these dimensions evolves in the fused one-workgroup
+// kernel (no Krylov basis is left in h->Vk then).
+bool evolve_fused(const ttn_handle* h, int DL, int DR, int DP, int sL, int sR, bool hasB, bool hasW) {
+    return (int64_t)DL * DR * DP <= SMALL_EVOLVE_N &&
+           small_evolve_doubles(DL, DR, DP, sL, sR, h->m, hasB, hasW) <= SMALL_EVOLVE_POOL;
+}
+bool node_evolve_fused(const ttn_handle* h, int v) {
+    const int s = sites_left(h, v);
+    return evolve_fused(h, h->DL[v], h->DR[v], h->DP[v], s, s, true, v != h->root);
+}
+bool bond_evolve_fused(const ttn_handle* h, int v) {
+    return evolve_fused(h, h->DP[v], 1, h->DP[v], h->scount[v], 0, false, true);
+}
+
 // x <- exp(-i tau Op) x by Lanczos (Arnoldi for the open system).  Small
 // operators run the whole evolution in one workgroup (FP64 in both modes).
 void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
-    if (n <= SMALL_EVOLVE_N &&
-        small_evolve_doubles(o.DL, o.DR, o.DP, o.sL, o.sR, h->m, o.Bb != nullptr, o.Wb != nullptr) <=
-            SMALL_EVOLVE_POOL) {
+    if (evolve_fused(h, o.DL, o.DR, o.DP, o.sL, o.sR, o.Bb != nullptr, o.Wb != nullptr)) {
         const int64_t L2 = (int64_t)o.DL * o.DL, R2 = (int64_t)o.DR * o.DR, P2 = (int64_t)o.DP * o.DP;
         chk(h, x, 2 * n, "krylov input");
         chk(h, o.Lb, 2 * (1 + o.sL) * L2, "L stack");
