@@ -310,6 +310,24 @@ def run_c5(steps):
     return out
 
 
+def run_bf16(w, steps, warmup):
+    """The BF16x3 precision mode on the same workload: timed steps and its
+    distance to the FP64 path after the same number of steps."""
+    import torch
+    from paper_2210_03763_amd import ttn
+    gb, ms, _, _, Fb, n2b, _ = run_gpu(w.copy(precision=ttn.PREC_BF16X3), steps, warmup, profile=False)
+    g64 = ttn.TTN(w.copy(precision=ttn.PREC_FP64), device="cuda:0")
+    g64.step(warmup + steps)
+    F64, _ = g64.fidelity()
+    ov = gb.overlap(g64)
+    out = {"ms_per_step": round(ms, 3), "steps_per_s": round(1e3 / ms, 4), "after_steps": warmup + steps,
+           "abs_dF_vs_fp64": abs(Fb - F64), "state_infidelity_C_vs_fp64": 1 - abs(ov) ** 2}
+    gb.close()
+    g64.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_open(w, steps, warmup, gamma):
     """Open-system mode (Eq. (eq:hoqs): -i gamma |r><r| per site, Arnoldi
     local exponentials) on the same workload: timed steps from the step
@@ -394,6 +412,8 @@ def main():
                     help="launch every step eagerly (for counter collection; kernels are the same)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--bf16-steps", type=int, default=0,
+                    help="also time the BF16x3 precision mode over this many steps")
     ap.add_argument("--c5-steps", type=int, default=0,
                     help="also measure the 8x8 d=4 chi=256 repetition-code program over this many steps")
     ap.add_argument("--contract-stage", choices=["A", "B", "C", "D"], default=None,
@@ -471,6 +491,9 @@ def main():
         print(f"[bench] open system: gamma {args.open_gamma}, {args.steps} steps", file=sys.stderr, flush=True)
         out["open_system"] = run_open(w, args.steps, args.warmup, args.open_gamma)
         out["open_system"]["closed_ms_per_step"] = round(ms_mixed, 3)
+    if args.bf16_steps > 0:
+        print(f"[bench] BF16x3 mode: {args.bf16_steps} steps", file=sys.stderr, flush=True)
+        out["bf16x3_variant"] = run_bf16(w, args.bf16_steps, args.warmup)
     if args.c5_steps > 0:
         print(f"[bench] chi=256 repetition code: {args.c5_steps} steps", file=sys.stderr, flush=True)
         out["chi256_repetition_code"] = run_c5(args.c5_steps)

@@ -55,12 +55,18 @@ extern "C" {
 #define TTN_ESTATE -5
 #define TTN_ENOTSUP -6
 
-/* Arithmetic of the effective-Hamiltonian contractions (the H_eff and
- * K_eff matvecs).  Lanczos scalars and re-orthogonalisation, the small
- * tridiagonal exponential, QR gauge moves, environment updates and the
- * master node tensors are FP64 in every mode. */
+/* Arithmetic of the tensor contractions.  TTN_PREC_FP64: everything in
+ * complex FP64.  TTN_PREC_FP32 (mixed): the H_eff / K_eff matvecs, the
+ * environment updates and the adjoint's exponential adjoints contract in
+ * complex FP32 with FP32 accumulation (results stored in FP64);
+ * TTN_PREC_BF16X3: as TTN_PREC_FP32, but the large contractions form every
+ * real product from bf16 pieces (x = hi + lo; hi*hi + hi*lo + lo*hi, about
+ * 2^-16 relative per product) on the bf16 matrix cores.  In every mode the
+ * Lanczos scalars and re-orthogonalisation, the small exponential, the QR
+ * gauge moves and the master node tensors are FP64. */
 #define TTN_PREC_FP64 0
 #define TTN_PREC_FP32 1
+#define TTN_PREC_BF16X3 2
 
 typedef struct ttn_handle ttn_handle;
 
@@ -229,7 +235,8 @@ int ttn_sample(ttn_handle* h, int64_t n_shots, uint64_t seed, int64_t shot0, voi
  * where (Op (x) leg x)[.., a, ..] = sum_b Op[a, b] x[.., b, ..], leg 0/1/2 =
  * left/right/parent of a (DL, DR, DP) tensor with the left index fastest.
  * Every array is planar complex (all real parts, then all imaginary parts)
- * in FP64 or FP32 (precision); Op_k are D x D column-major (D = dimension
+ * in FP64 or FP32 (precision: TTN_PREC_FP64, or TTN_PREC_FP32 / TTN_PREC_BF16X3
+ * on FP32 arrays); Op_k are D x D column-major (D = dimension
  * of the leg), stored one after another (2 D^2 reals each); x_k likewise
  * (2 DL DR DP reals each) when x_per_op != 0, otherwise one x is shared
  * (sum_ops requires x_per_op).  accumulate != 0 adds into y.  Enqueued on

@@ -400,6 +400,187 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, 
             }
 }
 
+// ---------------------------------------------------------------------------
+// BF16-split contraction (precision mode BF16x3): FP32 operands, every real
+// product from bf16 pieces x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) as
+// hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
+// (about 16 bits of each operand; relative error near 2^-16 per product),
+// combined into complex products by the same three-product form.  The tile
+// is staged once per 32-wide k-tile as six bf16 planes per operand (Re, Im,
+// Re + Im, each hi and lo), k-contiguous so that a lane reads its eight k
+// values with one 16-byte LDS load; single-buffered LDS, the next k-tile is
+// fetched into registers during the current one's products.  Operand lane
+// layout of the 16x16x32 instruction: lane l holds k = 8 (l / 16) .. +7 of
+// row (A) or column (B) l % 16; the output layout is that of 16x16x4.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int BM, int BN, int WGM, int WGN, bool AK, bool BKF>
+__global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> g, int tilesM, int tilesN,
+                                                                  int splits, int kchunk, float* partial) {
+    if (g.skip && *g.skip) return;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int BK = 32, KP = BK + 8;   // row stride in bf16: 80 bytes, 16-byte aligned rows
+    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int TI = WM / 16, TJ = WN / 16;
+    static_assert(TI >= 1 && TJ >= 1, "wave tile below 16 x 16");
+    constexpr int QA = BM * BK / NT, QB = BN * BK / NT;
+    static_assert(QA >= 1 && QB >= 1, "tile smaller than the block");
+    typedef f32x4 acc_t;
+    __shared__ __attribute__((aligned(16))) __bf16 As[6][BM][KP];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[6][BN][KP];
+    int64_t bid = blockIdx.x;
+    const int tm = bid % tilesM;
+    bid /= tilesM;
+    const int tn = bid % tilesN;
+    bid /= tilesN;
+    const int sp = bid % splits;
+    bid /= splits;
+    const int b = (int)bid;
+    const int b1 = b % g.B1, b2 = b / g.B1;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const float* A = g.A + b1 * g.sab1 + b2 * g.sab2 + (int64_t)m0 * g.sam;
+    const float* B = g.B + b1 * g.sbb1 + b2 * g.sbb2 + (int64_t)n0 * g.sbn;
+    const int K = g.Kin * g.Kout;
+    const int kb = sp * kchunk;
+    const int ke = min(K, kb + kchunk);
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
+    const float sa = g.conjA ? -1.0f : 1.0f, sb = g.conjB ? -1.0f : 1.0f;
+    const int mlim = g.M - m0, nlim = g.N - n0;
+    int offA[QA], offB[QB];
+    float mA[QA], mB[QB];
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+        const int e = tid + NT * q;
+        const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
+        const bool ok = mm < mlim;
+        mA[q] = ok ? 1.0f : 0.0f;
+        offA[q] = (ok ? mm : 0) * (int)g.sam + kk * (int)g.sak;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        const int e = tid + NT * q;
+        const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
+        const bool ok = nn < nlim;
+        mB[q] = ok ? 1.0f : 0.0f;
+        offB[q] = (ok ? nn : 0) * (int)g.sbn + kk * (int)g.sbk;
+    }
+    float pa[2][QA], pb[2][QB];
+    auto fetch = [&](int k0) {
+        const int kin = k0 % g.Kin, kout = k0 / g.Kin;
+        const float* Ab = A + (int64_t)kin * g.sak + (int64_t)kout * g.sako;
+        const float* Bb = B + (int64_t)kin * g.sbk + (int64_t)kout * g.sbko;
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            pa[0][q] = mA[q] * Ab[offA[q]];
+            pa[1][q] = (sa * mA[q]) * Ab[offA[q] + g.a_plane];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            pb[0][q] = mB[q] * Bb[offB[q]];
+            pb[1][q] = (sb * mB[q]) * Bb[offB[q] + g.b_plane];
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q;
+            const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
+            const float v[3] = {pa[0][q], pa[1][q], pa[0][q] + pa[1][q]};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const __bf16 hi = (__bf16)v[c];
+                As[2 * c][mm][kk] = hi;
+                As[2 * c + 1][mm][kk] = (__bf16)(v[c] - (float)hi);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + NT * q;
+            const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
+            const float v[3] = {pb[0][q], pb[1][q], pb[0][q] + pb[1][q]};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const __bf16 hi = (__bf16)v[c];
+                Bs[2 * c][nn][kk] = hi;
+                Bs[2 * c + 1][nn][kk] = (__bf16)(v[c] - (float)hi);
+            }
+        }
+    };
+    acc_t c1[TI][TJ], c2[TI][TJ], c3[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            c1[i][j] = acc_t{0, 0, 0, 0};
+            c2[i][j] = acc_t{0, 0, 0, 0};
+            c3[i][j] = acc_t{0, 0, 0, 0};
+        }
+    const int nt = (ke - kb) / BK;
+    const int kg = 8 * (lane / 16), c16 = lane % 16;
+    if (nt > 0) fetch(kb);
+    for (int t = 0; t < nt; ++t) {
+        __syncthreads();   // the previous tile's fragment reads are done
+        stash();
+        __syncthreads();
+        if (t + 1 < nt) fetch(kb + (t + 1) * BK);
+        bf16x8 bf[TJ][6];
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int p = 0; p < 6; ++p) bf[j][p] = *(const bf16x8*)&Bs[p][wn0 + 16 * j + c16][kg];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+            bf16x8 af[6];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) af[p] = *(const bf16x8*)&As[p][wm0 + 16 * i + c16][kg];
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+                // P1 = Re A Re B, P2 = Im A Im B, P3 = (Re + Im) A (Re + Im) B, each hi*hi + hi*lo + lo*hi
+                c1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[0], c1[i][j], 0, 0, 0);
+                c2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[2], c2[i][j], 0, 0, 0);
+                c3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][4], af[4], c3[i][j], 0, 0, 0);
+                c1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][1], af[0], c1[i][j], 0, 0, 0);
+                c2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][3], af[2], c2[i][j], 0, 0, 0);
+                c3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][5], af[4], c3[i][j], 0, 0, 0);
+                c1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[1], c1[i][j], 0, 0, 0);
+                c2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[3], c2[i][j], 0, 0, 0);
+                c3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][4], af[5], c3[i][j], 0, 0, 0);
+            }
+        }
+    }
+    const int64_t MN = (int64_t)g.M * g.N;
+    const int nbatch = g.B1 * g.B2;
+    float* C = g.C + b1 * g.scb1 + b2 * g.scb2;
+    float* P = partial + ((int64_t)sp * nbatch + b) * 2 * MN;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm0 + 16 * i + c16;
+                const int n = n0 + wn0 + 16 * j + 4 * (lane / 16) + r;
+                if (m >= g.M || n >= g.N) continue;
+                const float vre = c1[i][j][r] - c2[i][j][r];
+                const float vim = c3[i][j][r] - c1[i][j][r] - c2[i][j][r];
+                if (splits == 1) {
+                    const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
+                    float re = g.alpha * vre, im = g.alpha * vim;
+                    if (g.beta) {
+                        re += C[off];
+                        im += C[off + g.c_plane];
+                    }
+                    C[off] = re;
+                    C[off + g.c_plane] = im;
+                } else {
+                    P[m + (int64_t)g.M * n] = vre;
+                    P[MN + m + (int64_t)g.M * n] = vim;
+                }
+            }
+}
+
 // Largest element offset an operand can touch (all strides are >= 0).
 inline bool inside(const GemmScratch& ws, const void* base, int64_t max_off, int64_t plane, int esz) {
     if (!ws.regions) return true;
@@ -464,7 +645,10 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         // FP32 large tiles take 32-wide k-tiles (half the barriers) where the
         // inner contraction extent allows them
         const int kq = (sizeof(R) == 4 && big && g.Kin % 32 == 0) ? 32 : 16;
-        const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
+        // the BF16-split kernel covers 64 x 128 tiles
+        const bool bf16 = sizeof(R) == 4 && g.split && big && kq == 32;
+        const int TBM = bf16 ? 64 : BM;
+        const int tilesM = (g.M + TBM - 1) / TBM, tilesN = (g.N + BN - 1) / BN;
         const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
         int splits = 1;
         const int ktiles = K / 16;
@@ -502,22 +686,44 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
             hipLaunchKernelGGL((k_cgemm_mfma<R, bm, bn, wgm, wgn, minb, bk, false, false>), grid, blk, 0, s, \
                                g, tilesM, tilesN, splits, kchunk, part);                                   \
     } while (0)
-        // large tiles: 8 waves (2 x 4) per block, one block per CU; small
-        // tiles: 4 waves (2 x 2), two blocks per CU
+        // large tiles: 16 waves (4 x 4) per block, one block per CU (FP32 waves
+        // own 32 x 32 outputs, FP64 waves 32 x 16); small tiles: 4 waves
+        // (2 x 2), two blocks per CU
+#define TTN_BF16_LAUNCH(bm, bn, wgm, wgn)                                                                   \
+    do {                                                                                                   \
+        const dim3 blk(64 * wgm * wgn);                                                                    \
+        if (a_k && b_k)                                                                                    \
+            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, true, true>), grid, blk, 0, s, g, tilesM,   \
+                               tilesN, splits, kchunk, part);                                              \
+        else if (a_k)                                                                                      \
+            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, true, false>), grid, blk, 0, s, g, tilesM,  \
+                               tilesN, splits, kchunk, part);                                              \
+        else if (b_k)                                                                                      \
+            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, false, true>), grid, blk, 0, s, g, tilesM,  \
+                               tilesN, splits, kchunk, part);                                              \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, false, false>), grid, blk, 0, s, g, tilesM, \
+                               tilesN, splits, kchunk, part);                                              \
+    } while (0)
         if constexpr (sizeof(R) == 4) {
-            if (BM == 128 && kq == 32)
-                TTN_MFMA_LAUNCH(128, 128, 2, 4, 1, 32);
+            // BF16x3 mode: the large tiles with 32-wide k-tiles take the split
+            // products; the small shapes stay FP32
+            if (bf16)
+                TTN_BF16_LAUNCH(64, 128, 2, 4);
+            else if (BM == 128 && kq == 32)
+                TTN_MFMA_LAUNCH(128, 128, 4, 4, 1, 32);
             else if (BM == 128)
-                TTN_MFMA_LAUNCH(128, 128, 2, 4, 1, 16);
+                TTN_MFMA_LAUNCH(128, 128, 4, 4, 1, 16);
             else
                 TTN_MFMA_LAUNCH(64, 64, 2, 2, 2, 16);
         } else {
             if (BM == 128)
-                TTN_MFMA_LAUNCH(128, 64, 2, 4, 1, 16);
+                TTN_MFMA_LAUNCH(128, 64, 4, 4, 1, 16);
             else
                 TTN_MFMA_LAUNCH(64, 64, 2, 2, 2, 16);
         }
 #undef TTN_MFMA_LAUNCH
+#undef TTN_BF16_LAUNCH
         if (ev1) (void)hipEventRecord(ev1, s);
         if (splits > 1) {
             const int64_t total = (int64_t)g.M * g.N * nbatch;

@@ -68,6 +68,7 @@ struct ttn_handle {
     int N = 0, d = 0, chi = 0, m = 0, prec = 0;
     double c6 = 1, rcut = 0, leak = 0;
     double gamma = 0;       // Rydberg decay rate (open system); > 0 selects Arnoldi
+    bool split_bf16 = false; // BF16x3 products in the FP32 contractions
     bool nonherm = false;
     hipStream_t stream = nullptr;
     std::string err;
@@ -294,7 +295,9 @@ struct Ctx {
             const double fl = 8.0 * g.M * g.N * (double)g.Kin * g.Kout * (double)g.B1 * g.B2;
             h->prof_recs.push_back({idx, sizeof(R) == 4 ? 1 : 0, fl, h->in_heff});
         }
-        if (!cgemm<R>(g, h->gs, h->stream, why, sizeof(why), e0, e1))
+        Gemm<R> gg = g;
+        if (sizeof(R) == 4 && h->split_bf16) gg.split = 1;
+        if (!cgemm<R>(gg, h->gs, h->stream, why, sizeof(why), e0, e1))
             throw StatusError{TTN_EINVAL, std::string("launch extent check failed: ") + why};
     }
 };
@@ -1428,7 +1431,7 @@ void validate(const ttn_config* c) {
     if (c->chi < 1 || c->chi > 256) throw StatusError{TTN_EINVAL, "chi must be in [1, 256]"};
     if (c->krylov_dim < 1 || c->krylov_dim > KRYLOV_MAX)
         throw StatusError{TTN_EINVAL, "krylov_dim must be in [1, 16]"};
-    if (c->precision != TTN_PREC_FP64 && c->precision != TTN_PREC_FP32)
+    if (c->precision != TTN_PREC_FP64 && c->precision != TTN_PREC_FP32 && c->precision != TTN_PREC_BF16X3)
         throw StatusError{TTN_EINVAL, "unknown precision"};
     if (!c->pos_xy || !c->leaf_order || !c->init_product)
         throw StatusError{TTN_EINVAL, "missing positions, leaf order or initial product state"};
@@ -1452,7 +1455,9 @@ void setup_config(ttn_handle* h, const ttn_config* c) {
     h->d = c->d;
     h->chi = c->chi;
     h->m = c->krylov_dim;
-    h->prec = c->precision;
+    // BF16x3 runs the mixed path with split-product contractions
+    h->prec = c->precision == TTN_PREC_BF16X3 ? TTN_PREC_FP32 : c->precision;
+    h->split_bf16 = c->precision == TTN_PREC_BF16X3;
     h->c6 = c->c6;
     h->rcut = c->r_cut;
     h->leak = c->leak_ratio;
@@ -1894,15 +1899,17 @@ int ttn_leg_contract(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int
                      const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y, int32_t sum_ops,
                      int32_t accumulate, void* hip_stream) {
     try {
-        if (precision != TTN_PREC_FP64 && precision != TTN_PREC_FP32) return TTN_EINVAL;
+        if (precision != TTN_PREC_FP64 && precision != TTN_PREC_FP32 && precision != TTN_PREC_BF16X3)
+            return TTN_EINVAL;
         if (leg < 0 || leg > 2 || DL < 1 || DR < 1 || DP < 1 || n_ops < 1 || !d_ops || !d_x || !d_y)
             return TTN_EINVAL;
         if (sum_ops && !x_per_op) return TTN_EINVAL;
         const int D = leg == 0 ? DL : (leg == 1 ? DR : DP);
         const int64_t n = (int64_t)DL * DR * DP, D2 = (int64_t)D * D;
-        const size_t esz = precision == TTN_PREC_FP32 ? 4 : 8;
+        const size_t esz = precision == TTN_PREC_FP64 ? 8 : 4;
         ttn_handle h;
         h.stream = (hipStream_t)hip_stream;
+        h.split_bf16 = precision == TTN_PREC_BF16X3;
         // operand regions come from the argument sizes; split-K scratch is
         // allocated here for this call
         const int nx = x_per_op ? n_ops : 1, ny = sum_ops ? 1 : n_ops;
@@ -1913,7 +1920,7 @@ int ttn_leg_contract(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int
         HIPCHECK(hipMalloc(&h.gs.partial, h.gs.bytes));
         sort_regions(&h);
         try {
-            if (precision == TTN_PREC_FP32) {
+            if (precision != TTN_PREC_FP64) {
                 Ctx<float> c{&h, nullptr};
                 if (sum_ops)
                     leg_apply_sum<float>(c, leg, (const float*)d_ops, 2 * D2, (const float*)d_x, 2 * n, (float*)d_y,

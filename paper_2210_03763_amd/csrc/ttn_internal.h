@@ -32,6 +32,7 @@ struct Gemm {
     R alpha = 1;
     int beta = 0;                 // 0 overwrite, 1 accumulate
     const int* skip = nullptr;    // device flag: launch is a no-op when set
+    int split = 0;                // FP32 only: products from bf16 hi/lo splits (BF16x3)
 };
 
 // A device allocation [lo, hi) of the workspace, for launch extent checks.

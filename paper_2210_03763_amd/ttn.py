@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libttn.so")
 
 TTN_OK, TTN_EINVAL, TTN_ENOMEM, TTN_EDEVICE, TTN_ENUMERIC, TTN_ESTATE, TTN_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "ESTATE", -6: "ENOTSUP"}
 
