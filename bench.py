@@ -215,7 +215,7 @@ def run_adjoint(w, steps):
             "max_abs_grad": float(max(abs(go).max(), abs(gd).max()))}
 
 
-def run_contract_stage(stage, reps=5, chi=128):
+def run_contract_stage(stage, reps=5, chi=128, precision=1):
     """One H_eff stage of a 128^3 node as a single contraction launch through
     ttn_leg_contract (complex FP32), for kernel-level profiling: A = the left
     block and 16 left-site operators on a shared tensor, B = 16 right-site
@@ -238,14 +238,16 @@ def run_contract_stage(stage, reps=5, chi=128):
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        rc = L.ttn_leg_contract(1, leg, chi, chi, chi, K, ops.data_ptr(), x.data_ptr(), xpo, y.data_ptr(), sm, 0, st)
+        rc = L.ttn_leg_contract(precision, leg, chi, chi, chi, K, ops.data_ptr(), x.data_ptr(), xpo, y.data_ptr(),
+                                sm, 0, st)
         e1.record()
         torch.cuda.synchronize()
         assert rc == 0
         times.append(e0.elapsed_time(e1))
     ms = min(times[1:]) if reps > 1 else times[0]
     fl = 8.0 * n * chi * K
-    return {"contract_stage": stage, "shape": f"{chi}^3, {K} operators, leg {leg}", "ms": round(ms, 4),
+    return {"contract_stage": stage, "precision": {1: "fp32", 2: "bf16x3"}[precision],
+            "shape": f"{chi}^3, {K} operators, leg {leg}", "ms": round(ms, 4),
             "tflops_algorithmic": round(fl / ms / 1e9, 2), "reps": reps}
 
 
@@ -418,6 +420,8 @@ def main():
                     help="also measure the 8x8 d=4 chi=256 repetition-code program over this many steps")
     ap.add_argument("--contract-stage", choices=["A", "B", "C", "D"], default=None,
                     help="time one H_eff contraction stage of a 128^3 node instead (kernel profiling)")
+    ap.add_argument("--contract-precision", choices=["fp32", "bf16x3"], default="fp32",
+                    help="arithmetic of --contract-stage")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the TDVP sweep is sequential "
@@ -429,7 +433,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.contract_stage:
-        print(json.dumps(run_contract_stage(args.contract_stage)), flush=True)
+        print(json.dumps(run_contract_stage(args.contract_stage,
+                                            precision=2 if args.contract_precision == "bf16x3" else 1)), flush=True)
         return
     print(f"[bench] building workload {args.config}", file=sys.stderr, flush=True)
     w = W.config(args.config)

@@ -424,7 +424,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> 
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TI = WM / 16, TJ = WN / 16;
     static_assert(TI >= 1 && TJ >= 1, "wave tile below 16 x 16");
-    constexpr int QA = BM * BK / NT, QB = BN * BK / NT;
+    // each thread stages pairs of consecutive k (one 32-bit LDS store per plane)
+    constexpr int QA = BM * BK / (2 * NT), QB = BN * BK / (2 * NT);
     static_assert(QA >= 1 && QB >= 1, "tile smaller than the block");
     typedef f32x4 acc_t;
     __shared__ __attribute__((aligned(16))) __bf16 As[6][BM][KP];
@@ -448,64 +449,82 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> 
     const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
     const float sa = g.conjA ? -1.0f : 1.0f, sb = g.conjB ? -1.0f : 1.0f;
     const int mlim = g.M - m0, nlim = g.N - n0;
+    // slot q of a thread: row (m or n) and k pair 2 kp, 2 kp + 1
+    auto slotA = [&](int q, int& mm, int& kp) {
+        const int e = tid + NT * q;
+        mm = AK ? e / (BK / 2) : e % BM;
+        kp = AK ? e % (BK / 2) : e / BM;
+    };
+    auto slotB = [&](int q, int& nn, int& kp) {
+        const int e = tid + NT * q;
+        nn = BKF ? e / (BK / 2) : e % BN;
+        kp = BKF ? e % (BK / 2) : e / BN;
+    };
     int offA[QA], offB[QB];
     float mA[QA], mB[QB];
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
-        const int e = tid + NT * q;
-        const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
+        int mm, kp;
+        slotA(q, mm, kp);
         const bool ok = mm < mlim;
         mA[q] = ok ? 1.0f : 0.0f;
-        offA[q] = (ok ? mm : 0) * (int)g.sam + kk * (int)g.sak;
+        offA[q] = (ok ? mm : 0) * (int)g.sam + 2 * kp * (int)g.sak;
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-        const int e = tid + NT * q;
-        const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
+        int nn, kp;
+        slotB(q, nn, kp);
         const bool ok = nn < nlim;
         mB[q] = ok ? 1.0f : 0.0f;
-        offB[q] = (ok ? nn : 0) * (int)g.sbn + kk * (int)g.sbk;
+        offB[q] = (ok ? nn : 0) * (int)g.sbn + 2 * kp * (int)g.sbk;
     }
-    float pa[2][QA], pb[2][QB];
+    float pa[4][QA], pb[4][QB];   // [re k, re k+1, im k, im k+1]
     auto fetch = [&](int k0) {
         const int kin = k0 % g.Kin, kout = k0 / g.Kin;
         const float* Ab = A + (int64_t)kin * g.sak + (int64_t)kout * g.sako;
         const float* Bb = B + (int64_t)kin * g.sbk + (int64_t)kout * g.sbko;
+        const int64_t ka = g.sak, kbs = g.sbk;
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             pa[0][q] = mA[q] * Ab[offA[q]];
-            pa[1][q] = (sa * mA[q]) * Ab[offA[q] + g.a_plane];
+            pa[1][q] = mA[q] * Ab[offA[q] + ka];
+            pa[2][q] = (sa * mA[q]) * Ab[offA[q] + g.a_plane];
+            pa[3][q] = (sa * mA[q]) * Ab[offA[q] + ka + g.a_plane];
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             pb[0][q] = mB[q] * Bb[offB[q]];
-            pb[1][q] = (sb * mB[q]) * Bb[offB[q] + g.b_plane];
+            pb[1][q] = mB[q] * Bb[offB[q] + kbs];
+            pb[2][q] = (sb * mB[q]) * Bb[offB[q] + g.b_plane];
+            pb[3][q] = (sb * mB[q]) * Bb[offB[q] + kbs + g.b_plane];
         }
+    };
+    // planes 2c (hi) and 2c + 1 (lo) of value c in {Re, Im, Re + Im}, two k at once
+    auto put = [](__bf16* hi_dst, __bf16* lo_dst, float x0, float x1) {
+        const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+        const __bf16 l0 = (__bf16)(x0 - (float)h0), l1 = (__bf16)(x1 - (float)h1);
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        *(bf16x2*)hi_dst = bf16x2{h0, h1};
+        *(bf16x2*)lo_dst = bf16x2{l0, l1};
     };
     auto stash = [&]() {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
-            const int e = tid + NT * q;
-            const int mm = AK ? e / BK : e % BM, kk = AK ? e % BK : e / BM;
-            const float v[3] = {pa[0][q], pa[1][q], pa[0][q] + pa[1][q]};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const __bf16 hi = (__bf16)v[c];
-                As[2 * c][mm][kk] = hi;
-                As[2 * c + 1][mm][kk] = (__bf16)(v[c] - (float)hi);
-            }
+            int mm, kp;
+            slotA(q, mm, kp);
+            const int kk = 2 * kp;
+            put(&As[0][mm][kk], &As[1][mm][kk], pa[0][q], pa[1][q]);
+            put(&As[2][mm][kk], &As[3][mm][kk], pa[2][q], pa[3][q]);
+            put(&As[4][mm][kk], &As[5][mm][kk], pa[0][q] + pa[2][q], pa[1][q] + pa[3][q]);
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            const int e = tid + NT * q;
-            const int nn = BKF ? e / BK : e % BN, kk = BKF ? e % BK : e / BN;
-            const float v[3] = {pb[0][q], pb[1][q], pb[0][q] + pb[1][q]};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const __bf16 hi = (__bf16)v[c];
-                Bs[2 * c][nn][kk] = hi;
-                Bs[2 * c + 1][nn][kk] = (__bf16)(v[c] - (float)hi);
-            }
+            int nn, kp;
+            slotB(q, nn, kp);
+            const int kk = 2 * kp;
+            put(&Bs[0][nn][kk], &Bs[1][nn][kk], pb[0][q], pb[1][q]);
+            put(&Bs[2][nn][kk], &Bs[3][nn][kk], pb[2][q], pb[3][q]);
+            put(&Bs[4][nn][kk], &Bs[5][nn][kk], pb[0][q] + pb[2][q], pb[1][q] + pb[3][q]);
         }
     };
     acc_t c1[TI][TJ], c2[TI][TJ], c3[TI][TJ];
