@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <initializer_list>
 
 #include "ttn_internal.h"
 
@@ -412,20 +413,33 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, 
 // fetched into registers during the current one's products.  Operand lane
 // layout of the 16x16x32 instruction: lane l holds k = 8 (l / 16) .. +7 of
 // row (A) or column (B) l % 16; the output layout is that of 16x16x4.
+// Tiles are 128 x 128 over 8 waves (each wave 64 x 32, 120 KB of LDS, one
+// block per CU): with 64 x 128 tiles (about 5 complex multiply-adds per
+// operand byte fetched) the waves waited on operand fetch, and 128 x 128
+// tiles (8 per byte) measured 20-30% faster.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <int BM, int BN, int WGM, int WGN, bool AK, bool BKF>
 __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> g, int tilesM, int tilesN,
-                                                                  int splits, int kchunk, float* partial) {
+                                                                  int splits, int kchunk, float* partial,
+                                                                  int vec) {
     if (g.skip && *g.skip) return;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int BK = 32, KP = BK + 8;   // row stride in bf16: 80 bytes, 16-byte aligned rows
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TI = WM / 16, TJ = WN / 16;
     static_assert(TI >= 1 && TJ >= 1, "wave tile below 16 x 16");
-    // each thread stages pairs of consecutive k (one 32-bit LDS store per plane)
-    constexpr int QA = BM * BK / (2 * NT), QB = BN * BK / (2 * NT);
+    // Each thread stages four consecutive k of one row and writes them with
+    // one 64-bit LDS store per plane. Rows sit 20 dwords apart, so eight
+    // consecutive rows start on eight different 4-bank groups; for an
+    // index-fast operand lanes 0-7 take rows r..r+7 at k-quad q and lanes 8-15
+    // the same rows at q+1, which fills every bank once per 16 lanes, and a
+    // wavefront's global loads still cover 32 consecutive rows per k. For a
+    // k-fast operand eight lanes walk the 32 k of one row, and the rows of the
+    // 8-lane groups step by 4 (80 dwords, half the banks) so that 16 or 32
+    // lanes again touch every bank once.
+    constexpr int QA = BM * BK / (4 * NT), QB = BN * BK / (4 * NT);
     static_assert(QA >= 1 && QB >= 1, "tile smaller than the block");
     typedef f32x4 acc_t;
     __shared__ __attribute__((aligned(16))) __bf16 As[6][BM][KP];
@@ -449,82 +463,96 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> 
     const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
     const float sa = g.conjA ? -1.0f : 1.0f, sb = g.conjB ? -1.0f : 1.0f;
     const int mlim = g.M - m0, nlim = g.N - n0;
-    // slot q of a thread: row (m or n) and k pair 2 kp, 2 kp + 1
-    auto slotA = [&](int q, int& mm, int& kp) {
-        const int e = tid + NT * q;
-        mm = AK ? e / (BK / 2) : e % BM;
-        kp = AK ? e % (BK / 2) : e / BM;
-    };
-    auto slotB = [&](int q, int& nn, int& kp) {
-        const int e = tid + NT * q;
-        nn = BKF ? e / (BK / 2) : e % BN;
-        kp = BKF ? e % (BK / 2) : e / BN;
+    // slot e of an R-row tile -> row and k-quad (k = 4 kq .. 4 kq + 3)
+    auto slot = [&](int e, int R, bool kfast, int& row, int& kq) {
+        if (kfast) {
+            const int j = e / (BK / 4);
+            kq = e % (BK / 4);
+            row = 4 * (j % 4) + (j / 4) % 4 + 16 * (j / 16);
+        } else {
+            const int rest = e / 16;
+            row = e % 8 + 8 * (rest % (R / 8));
+            kq = (e / 8) % 2 + 2 * (rest / (R / 8));
+        }
     };
     int offA[QA], offB[QB];
     float mA[QA], mB[QB];
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
-        int mm, kp;
-        slotA(q, mm, kp);
+        int mm, kq;
+        slot(tid + NT * q, BM, AK, mm, kq);
         const bool ok = mm < mlim;
         mA[q] = ok ? 1.0f : 0.0f;
-        offA[q] = (ok ? mm : 0) * (int)g.sam + 2 * kp * (int)g.sak;
+        offA[q] = (ok ? mm : 0) * (int)g.sam + 4 * kq * (int)g.sak;
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-        int nn, kp;
-        slotB(q, nn, kp);
+        int nn, kq;
+        slot(tid + NT * q, BN, BKF, nn, kq);
         const bool ok = nn < nlim;
         mB[q] = ok ? 1.0f : 0.0f;
-        offB[q] = (ok ? nn : 0) * (int)g.sbn + 2 * kp * (int)g.sbk;
+        offB[q] = (ok ? nn : 0) * (int)g.sbn + 4 * kq * (int)g.sbk;
     }
-    float pa[4][QA], pb[4][QB];   // [re k, re k+1, im k, im k+1]
+    constexpr int QM = QA > QB ? QA : QB;
+    float pa[8][QM], pb[8][QM];   // [re k .. k+3, im k .. k+3]
     auto fetch = [&](int k0) {
         const int kin = k0 % g.Kin, kout = k0 / g.Kin;
         const float* Ab = A + (int64_t)kin * g.sak + (int64_t)kout * g.sako;
         const float* Bb = B + (int64_t)kin * g.sbk + (int64_t)kout * g.sbko;
-        const int64_t ka = g.sak, kbs = g.sbk;
+        const int ka = (int)g.sak, kbs = (int)g.sbk;
+        // a k-fast quad is one 16-byte load where the host found it aligned
+        auto quad = [&](const float* src, int stride, bool v, float scale, float (*dst)[QM], int q) {
+            if (v) {
+                const float4 t = *(const float4*)src;
+                dst[0][q] = scale * t.x;
+                dst[1][q] = scale * t.y;
+                dst[2][q] = scale * t.z;
+                dst[3][q] = scale * t.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dst[j][q] = scale * src[j * stride];
+            }
+        };
+        const bool va = AK && (vec & 1), vb = BKF && (vec & 2);
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
-            pa[0][q] = mA[q] * Ab[offA[q]];
-            pa[1][q] = mA[q] * Ab[offA[q] + ka];
-            pa[2][q] = (sa * mA[q]) * Ab[offA[q] + g.a_plane];
-            pa[3][q] = (sa * mA[q]) * Ab[offA[q] + ka + g.a_plane];
+            quad(Ab + offA[q], ka, va, mA[q], pa, q);
+            quad(Ab + offA[q] + g.a_plane, ka, va, sa * mA[q], pa + 4, q);
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            pb[0][q] = mB[q] * Bb[offB[q]];
-            pb[1][q] = mB[q] * Bb[offB[q] + kbs];
-            pb[2][q] = (sb * mB[q]) * Bb[offB[q] + g.b_plane];
-            pb[3][q] = (sb * mB[q]) * Bb[offB[q] + kbs + g.b_plane];
+            quad(Bb + offB[q], kbs, vb, mB[q], pb, q);
+            quad(Bb + offB[q] + g.b_plane, kbs, vb, sb * mB[q], pb + 4, q);
         }
     };
-    // planes 2c (hi) and 2c + 1 (lo) of value c in {Re, Im, Re + Im}, two k at once
-    auto put = [](__bf16* hi_dst, __bf16* lo_dst, float x0, float x1) {
-        const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
-        const __bf16 l0 = (__bf16)(x0 - (float)h0), l1 = (__bf16)(x1 - (float)h1);
-        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-        *(bf16x2*)hi_dst = bf16x2{h0, h1};
-        *(bf16x2*)lo_dst = bf16x2{l0, l1};
+    // planes 2c (hi) and 2c + 1 (lo) of value c in {Re, Im, Re + Im}, four k at once
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    auto put = [](__bf16* hi_dst, __bf16* lo_dst, float x0, float x1, float x2, float x3) {
+        const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1, h2 = (__bf16)x2, h3 = (__bf16)x3;
+        *(bf16x4*)hi_dst = bf16x4{h0, h1, h2, h3};
+        *(bf16x4*)lo_dst = bf16x4{(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1), (__bf16)(x2 - (float)h2),
+                                  (__bf16)(x3 - (float)h3)};
     };
     auto stash = [&]() {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
-            int mm, kp;
-            slotA(q, mm, kp);
-            const int kk = 2 * kp;
-            put(&As[0][mm][kk], &As[1][mm][kk], pa[0][q], pa[1][q]);
-            put(&As[2][mm][kk], &As[3][mm][kk], pa[2][q], pa[3][q]);
-            put(&As[4][mm][kk], &As[5][mm][kk], pa[0][q] + pa[2][q], pa[1][q] + pa[3][q]);
+            int mm, kq;
+            slot(tid + NT * q, BM, AK, mm, kq);
+            const int kk = 4 * kq;
+            put(&As[0][mm][kk], &As[1][mm][kk], pa[0][q], pa[1][q], pa[2][q], pa[3][q]);
+            put(&As[2][mm][kk], &As[3][mm][kk], pa[4][q], pa[5][q], pa[6][q], pa[7][q]);
+            put(&As[4][mm][kk], &As[5][mm][kk], pa[0][q] + pa[4][q], pa[1][q] + pa[5][q], pa[2][q] + pa[6][q],
+                pa[3][q] + pa[7][q]);
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            int nn, kp;
-            slotB(q, nn, kp);
-            const int kk = 2 * kp;
-            put(&Bs[0][nn][kk], &Bs[1][nn][kk], pb[0][q], pb[1][q]);
-            put(&Bs[2][nn][kk], &Bs[3][nn][kk], pb[2][q], pb[3][q]);
-            put(&Bs[4][nn][kk], &Bs[5][nn][kk], pb[0][q] + pb[2][q], pb[1][q] + pb[3][q]);
+            int nn, kq;
+            slot(tid + NT * q, BN, BKF, nn, kq);
+            const int kk = 4 * kq;
+            put(&Bs[0][nn][kk], &Bs[1][nn][kk], pb[0][q], pb[1][q], pb[2][q], pb[3][q]);
+            put(&Bs[2][nn][kk], &Bs[3][nn][kk], pb[4][q], pb[5][q], pb[6][q], pb[7][q]);
+            put(&Bs[4][nn][kk], &Bs[5][nn][kk], pb[0][q] + pb[4][q], pb[1][q] + pb[5][q], pb[2][q] + pb[6][q],
+                pb[3][q] + pb[7][q]);
         }
     };
     acc_t c1[TI][TJ], c2[TI][TJ], c3[TI][TJ];
@@ -664,10 +692,8 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         // FP32 large tiles take 32-wide k-tiles (half the barriers) where the
         // inner contraction extent allows them
         const int kq = (sizeof(R) == 4 && big && g.Kin % 32 == 0) ? 32 : 16;
-        // the BF16-split kernel covers 64 x 128 tiles
         const bool bf16 = sizeof(R) == 4 && g.split && big && kq == 32;
-        const int TBM = bf16 ? 64 : BM;
-        const int tilesM = (g.M + TBM - 1) / TBM, tilesN = (g.N + BN - 1) / BN;
+        const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
         const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
         int splits = 1;
         const int ktiles = K / 16;
@@ -688,6 +714,16 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         }
         const dim3 grid((unsigned)(tiles * splits));
         R* part = (R*)ws.partial;
+        // BF16 path: k-fast operands whose k quads are 16-byte aligned load
+        // them as one vector (k tiles start at multiples of 32 in Kin)
+        auto quads = [](const void* p, std::initializer_list<int64_t> strides) {
+            if ((uintptr_t)p % 16) return false;
+            for (int64_t st : strides)
+                if (st % 4) return false;
+            return true;
+        };
+        const int vec = (a_k && quads(g.A, {g.sam, g.sako, g.sab1, g.sab2, g.a_plane}) ? 1 : 0) |
+                        (b_k && quads(g.B, {g.sbn, g.sbko, g.sbb1, g.sbb2, g.b_plane}) ? 2 : 0);
         if (ev0) (void)hipEventRecord(ev0, s);
 #define TTN_MFMA_LAUNCH(bm, bn, wgm, wgn, minb, bk)                                                        \
     do {                                                                                                   \
@@ -713,22 +749,22 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         const dim3 blk(64 * wgm * wgn);                                                                    \
         if (a_k && b_k)                                                                                    \
             hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, true, true>), grid, blk, 0, s, g, tilesM,   \
-                               tilesN, splits, kchunk, part);                                              \
+                               tilesN, splits, kchunk, part, vec);                                              \
         else if (a_k)                                                                                      \
             hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, true, false>), grid, blk, 0, s, g, tilesM,  \
-                               tilesN, splits, kchunk, part);                                              \
+                               tilesN, splits, kchunk, part, vec);                                              \
         else if (b_k)                                                                                      \
             hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, false, true>), grid, blk, 0, s, g, tilesM,  \
-                               tilesN, splits, kchunk, part);                                              \
+                               tilesN, splits, kchunk, part, vec);                                              \
         else                                                                                               \
             hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, false, false>), grid, blk, 0, s, g, tilesM, \
-                               tilesN, splits, kchunk, part);                                              \
+                               tilesN, splits, kchunk, part, vec);                                              \
     } while (0)
         if constexpr (sizeof(R) == 4) {
             // BF16x3 mode: the large tiles with 32-wide k-tiles take the split
             // products; the small shapes stay FP32
             if (bf16)
-                TTN_BF16_LAUNCH(64, 128, 2, 4);
+                TTN_BF16_LAUNCH(128, 128, 2, 4);
             else if (BM == 128 && kq == 32)
                 TTN_MFMA_LAUNCH(128, 128, 4, 4, 1, 32);
             else if (BM == 128)

@@ -27,8 +27,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("leg,K,xpo,sm", [(0, 17, 0, 0), (1, 16, 0, 0), (1, 17, 1, 1), (2, 33, 1, 1)])
-def test_bf16x3_stage_accuracy(leg, K, xpo, sm):
+@pytest.mark.parametrize("leg,K,xpo,sm,shift", [(0, 17, 0, 0, 0), (1, 16, 0, 0, 0), (1, 17, 1, 1, 0), (2, 33, 1, 1, 0),
+                                                (0, 17, 0, 0, 1), (2, 33, 1, 1, 1)])
+def test_bf16x3_stage_accuracy(leg, K, xpo, sm, shift):
+    """shift = 1 moves both operands one element off 16-byte alignment, which
+    takes the k-fast operands off the vector-load path."""
     L = T.lib()
     L.ttn_leg_contract.restype = C.c_int
     L.ttn_leg_contract.argtypes = [C.c_int32] * 6 + [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
@@ -41,7 +44,10 @@ def test_bf16x3_stage_accuracy(leg, K, xpo, sm):
     outs = {}
     st = torch.cuda.current_stream().cuda_stream
     for prec, dt in ((T.PREC_FP64, torch.float64), (T.PREC_BF16X3, torch.float32), (T.PREC_FP32, torch.float32)):
-        o, xx = ops.to(dt), x.to(dt)
+        o = torch.zeros(ops.numel() + shift, dtype=dt, device="cuda")[shift:].view_as(ops)
+        xx = torch.zeros(x.numel() + shift, dtype=dt, device="cuda")[shift:].view_as(x)
+        o.copy_(ops)
+        xx.copy_(x)
         y = torch.zeros(1 if sm else K, 2 * n, dtype=dt, device="cuda")
         rc = L.ttn_leg_contract(prec, leg, chi, chi, chi, K, o.data_ptr(), xx.data_ptr(), xpo, y.data_ptr(), sm, 0, st)
         torch.cuda.synchronize()
@@ -51,7 +57,7 @@ def test_bf16x3_stage_accuracy(leg, K, xpo, sm):
     scale = ref.abs().max().item()
     e16 = (outs[T.PREC_BF16X3] - ref).abs().max().item() / scale
     e32 = (outs[T.PREC_FP32] - ref).abs().max().item() / scale
-    _say(f"[bf16] leg {leg} K {K}: relative max error bf16x3 {e16:.2e}, fp32 {e32:.2e}")
+    _say(f"[bf16] leg {leg} K {K} shift {shift}: relative max error bf16x3 {e16:.2e}, fp32 {e32:.2e}")
     assert e16 < 1e-4
     assert e16 > e32   # the split really ran
 
