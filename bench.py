@@ -16,7 +16,9 @@ Beside the headline line's fields the JSON carries: fp64_path (the FP64
 path over the same steps and its distance to the mixed result),
 forward_adjoint (recorded steps and the backward pass of the fidelity
 gradient, mixed and FP64), open_system (the same workload with Rydberg
-decay), sampling (10^6 projective-measurement shots) and cpu_baseline.
+decay), sampling (10^6 projective-measurement shots), bf16x3_variant (the
+BF16x3 precision mode over the same workload and its distance to the FP64
+path) and cpu_baseline.
 """
 from __future__ import annotations
 
@@ -414,7 +416,7 @@ def main():
                     help="launch every step eagerly (for counter collection; kernels are the same)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
-    ap.add_argument("--bf16-steps", type=int, default=0,
+    ap.add_argument("--bf16-steps", type=int, default=2,
                     help="also time the BF16x3 precision mode over this many steps")
     ap.add_argument("--c5-steps", type=int, default=0,
                     help="also measure the 8x8 d=4 chi=256 repetition-code program over this many steps")
