@@ -314,12 +314,13 @@ def run_c5(steps):
     return out
 
 
-def run_bf16(w, steps, warmup):
+def run_bf16(w, steps, warmup, graphs=True):
     """The BF16x3 precision mode on the same workload: timed steps and its
     distance to the FP64 path after the same number of steps."""
     import torch
     from paper_2210_03763_amd import ttn
-    gb, ms, _, _, Fb, n2b, _ = run_gpu(w.copy(precision=ttn.PREC_BF16X3), steps, warmup, profile=False)
+    gb, ms, _, _, Fb, n2b, _ = run_gpu(w.copy(precision=ttn.PREC_BF16X3), steps, warmup, profile=False,
+                                       graphs=graphs)
     g64 = ttn.TTN(w.copy(precision=ttn.PREC_FP64), device="cuda:0")
     g64.step(warmup + steps)
     F64, _ = g64.fidelity()
@@ -500,7 +501,7 @@ def main():
         out["open_system"]["closed_ms_per_step"] = round(ms_mixed, 3)
     if args.bf16_steps > 0:
         print(f"[bench] BF16x3 mode: {args.bf16_steps} steps", file=sys.stderr, flush=True)
-        out["bf16x3_variant"] = run_bf16(w, args.bf16_steps, args.warmup)
+        out["bf16x3_variant"] = run_bf16(w, args.bf16_steps, args.warmup, graphs=not args.no_graphs)
     if args.c5_steps > 0:
         print(f"[bench] chi=256 repetition code: {args.c5_steps} steps", file=sys.stderr, flush=True)
         out["chi256_repetition_code"] = run_c5(args.c5_steps)
