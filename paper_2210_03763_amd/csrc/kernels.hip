@@ -33,12 +33,13 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;   // valid in thread 0
 }
 
-// Sums 32 values over the block with one barrier: a butterfly inside each
-// wave leaves value ((l>>5)&1)*16 + ((l>>4)&1)*8 + ((l>>3)&1)*4 + ((l>>2)&1)*2
-// + ((l>>1)&1) in lane l, the waves' results meet in sh (32 per wave).
-// Returns the block total of value threadIdx.x in threads 0..31.
-template <int H>
-__device__ inline void butterfly_step(double (&a)[32], int lane) {
+// Sums P values (P a power of two, 2 <= P <= 32) over the block with one
+// barrier: a butterfly inside each wave leaves value (l >> 1) & (P - 1),
+// summed over the wave, in lane l; the waves' results meet in sh (P per wave,
+// at most four waves).  Returns the block total of value threadIdx.x in
+// threads 0 .. P-1.
+template <int H, int P>
+__device__ inline void butterfly_step(double (&a)[P], int lane) {
     // lanes that differ in bit 2H exchange one half of their first 2H values
     const bool hi = (lane & (2 * H)) != 0;
 #pragma unroll
@@ -49,23 +50,35 @@ __device__ inline void butterfly_step(double (&a)[32], int lane) {
     }
 }
 
-__device__ inline double block_sum32(double (&a)[32], double* sh) {
+template <int P>
+__device__ inline double block_sum_p(double (&a)[P], double* sh) {
+    static_assert(P >= 2 && P <= 32 && (P & (P - 1)) == 0, "P must be a power of two in [2, 32]");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    butterfly_step<16>(a, lane);
-    butterfly_step<8>(a, lane);
-    butterfly_step<4>(a, lane);
-    butterfly_step<2>(a, lane);
+    if constexpr (P >= 32) butterfly_step<16>(a, lane);
+    if constexpr (P >= 16) butterfly_step<8>(a, lane);
+    if constexpr (P >= 8) butterfly_step<4>(a, lane);
+    if constexpr (P >= 4) butterfly_step<2>(a, lane);
     butterfly_step<1>(a, lane);
     a[0] += __shfl_xor(a[0], 1, 64);
-    const int idx = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
-                    ((lane >> 1) & 1);
+#pragma unroll
+    for (int b = 2 * P; b < 64; b <<= 1) a[0] += __shfl_xor(a[0], b, 64);
+    const int idx = (lane >> 1) & (P - 1);
     __syncthreads();
-    if ((lane & 1) == 0) sh[32 * wv + idx] = a[0];
+    if ((lane & 1) == 0 && lane < 2 * P) sh[P * wv + idx] = a[0];
     __syncthreads();
     double r = 0;
-    if (threadIdx.x < 32)
-        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) r += sh[32 * w2 + threadIdx.x];
+    if (threadIdx.x < P)
+        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) r += sh[P * w2 + threadIdx.x];
     return r;
+}
+
+__device__ inline double block_sum32(double (&a)[32], double* sh) { return block_sum_p<32>(a, sh); }
+
+// smallest power of two >= 2 kc
+constexpr int pow2_pairs(int kc) {
+    int p = 2;
+    while (p < 2 * kc) p *= 2;
+    return p;
 }
 
 __global__ void k_norm2_partial(const double* x, int64_t n, double* partial, const int* skip) {
@@ -81,9 +94,21 @@ __global__ void k_norm2_partial(const double* x, int64_t n, double* partial, con
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
+// Sum of p[start], p[start + step], ... below count, with eight loads in
+// flight per thread (independent accumulators) instead of one.
+__device__ inline double strided_sum(const double* p, int count, int start, int step) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = start;
+    for (; i + 7 * step < count; i += 8 * step) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += p[i + u * step];
+    }
+    for (; i < count; i += step) acc[0] += p[i];
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 __device__ inline double wave_sum_partials(const double* partial, int nb) {
-    double s = 0;
-    for (int i = threadIdx.x; i < nb; i += 64) s += partial[i];
+    double s = strided_sum(partial, nb, threadIdx.x, 64);
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     return s;   // valid in lane 0
 }
@@ -119,23 +144,26 @@ __global__ void k_scale_by(const double* x, int64_t n, double* y, const LanczosD
     }
 }
 
-// partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < kcount; with wf != nullptr
-// w is first widened from the FP32 matvec output wf (and stored)
-__global__ __launch_bounds__(256) void k_multidot_partial(const double* V, int kcount, const double* w, int64_t n,
+// partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < KC (2 KC reals per
+// block); with wf != nullptr w is first widened from the FP32 matvec output
+// wf (and stored).  KC is a template argument so that the per-thread arrays
+// hold exactly the vectors in use.
+template <int KC>
+__global__ __launch_bounds__(256) void k_multidot_partial(const double* V, const double* w, int64_t n,
                                                          double* partial, const LanczosDev* lz, const float* wf) {
     if (lz->done) return;
-    __shared__ double sh32[4 * 32];
-    double re[KRYLOV_MAX], im[KRYLOV_MAX];
-    for (int k = 0; k < KRYLOV_MAX; ++k) re[k] = im[k] = 0;
+    constexpr int P = pow2_pairs(KC);
+    __shared__ double shp[4 * P];
+    double re[KC], im[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) re[k] = im[k] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        double vr[KRYLOV_MAX], vi[KRYLOV_MAX];
+        double vr[KC], vi[KC];
 #pragma unroll
-        for (int k = 0; k < KRYLOV_MAX; ++k) {
-            if (k < kcount) {
-                vr[k] = V[2 * n * k + i];
-                vi[k] = V[2 * n * k + n + i];
-            }
+        for (int k = 0; k < KC; ++k) {
+            vr[k] = V[2 * n * k + i];
+            vi[k] = V[2 * n * k + n + i];
         }
         double wr, wi;
         if (wf) {
@@ -148,116 +176,126 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* V, int k
             wi = w[i + n];
         }
 #pragma unroll
-        for (int k = 0; k < KRYLOV_MAX; ++k) {
-            if (k < kcount) {
-                re[k] += vr[k] * wr + vi[k] * wi;
-                im[k] += vr[k] * wi - vi[k] * wr;
-            }
+        for (int k = 0; k < KC; ++k) {
+            re[k] += vr[k] * wr + vi[k] * wi;
+            im[k] += vr[k] * wi - vi[k] * wr;
         }
     }
-    double a[32];
+    double a[P];
 #pragma unroll
-    for (int k = 0; k < KRYLOV_MAX; ++k) {
-        a[2 * k] = re[k];
-        a[2 * k + 1] = im[k];
+    for (int k = 0; k < P / 2; ++k) {
+        a[2 * k] = k < KC ? re[k] : 0.0;
+        a[2 * k + 1] = k < KC ? im[k] : 0.0;
     }
-    const double t = block_sum32(a, sh32);
-    if (threadIdx.x < 2 * kcount) partial[blockIdx.x * KRYLOV_MAX * 2 + threadIdx.x] = t;
+    const double t = block_sum_p<P>(a, shp);
+    if (threadIdx.x < 2 * KC) partial[blockIdx.x * 2 * KC + threadIdx.x] = t;
 }
 
-__global__ void k_multidot_final(const double* partial, int nb, int kcount, LanczosDev* lz,
-                                 int alpha_index) {
+// Totals of the 2 kcount reals per block (layout of k_multidot_partial) into
+// the Lanczos state.  1024 threads: thread (g, v) = (t / 32, t % 32) sums value
+// v of blocks g, g + 32, ..., so that each step of the 32 groups reads one
+// contiguous stretch of the partials.
+__global__ __launch_bounds__(1024) void k_multidot_final(const double* partial, int nb, int kcount,
+                                                         LanczosDev* lz, int alpha_index) {
     if (lz->done) return;
-    // wave k sums the partials of vector k (lanes stride over blocks)
-    const int k = threadIdx.x / 64, lane = threadIdx.x % 64;
-    if (k >= kcount) return;
-    double re = 0, im = 0;
-    for (int b = lane; b < nb; b += 64) {
-        re += partial[(b * KRYLOV_MAX + k) * 2];
-        im += partial[(b * KRYLOV_MAX + k) * 2 + 1];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_down(re, o, 64);
-        im += __shfl_down(im, o, 64);
-    }
-    if (lane == 0) {
-        lz->c[2 * k] = re;
-        lz->c[2 * k + 1] = im;
-        if (k == alpha_index) {
-            lz->alpha[k] = re;
-            lz->m_eff = k + 1;
+    __shared__ double sh[32][33];
+    __shared__ double tot[32];
+    const int v = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int nv = 2 * kcount;
+    double acc = 0;
+    if (v < nv) {
+        double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int b = g;
+        for (; b + 7 * 32 < nb; b += 8 * 32) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] += partial[(int64_t)(b + 32 * q) * nv + v];
         }
-        if (lz->nonherm) {
-            // Hessenberg column kcount - 1: the first pass (alpha_index >= 0)
-            // sets it, the second Gram-Schmidt pass adds its projections
-            double* hp = lz->hs + 2 * ((kcount - 1) * KRYLOV_MAX + k);
-            if (alpha_index >= 0) {
-                hp[0] = re;
-                hp[1] = im;
-            } else {
-                hp[0] += re;
-                hp[1] += im;
-            }
+        for (; b < nb; b += 32) u[0] += partial[(int64_t)b * nv + v];
+        acc = ((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7]));
+    }
+    sh[g][v] = acc;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double r = 0;
+        for (int q = 0; q < 32; ++q) r += sh[q][threadIdx.x];
+        tot[threadIdx.x] = r;
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k >= kcount) return;
+    const double re = tot[2 * k], im = tot[2 * k + 1];
+    lz->c[2 * k] = re;
+    lz->c[2 * k + 1] = im;
+    if (k == alpha_index) {
+        lz->alpha[k] = re;
+        lz->m_eff = k + 1;
+    }
+    if (lz->nonherm) {
+        // Hessenberg column kcount - 1: the first pass (alpha_index >= 0)
+        // sets it, the second Gram-Schmidt pass adds its projections
+        double* hp = lz->hs + 2 * ((kcount - 1) * KRYLOV_MAX + k);
+        if (alpha_index >= 0) {
+            hp[0] = re;
+            hp[1] = im;
+        } else {
+            hp[0] += re;
+            hp[1] += im;
         }
     }
 }
 
 // w -= sum_k c_k V_k; then, per block, partial sums of either the new
-// projections conj(V_k) w (mode 1) or |w|^2 (mode 2); mode 0 only subtracts.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_sub_fused(const double* V, int kcount, double* w, int64_t n,
-                                                   double* partial, const LanczosDev* lz) {
+// projections conj(V_k) w (mode 1, 2 KC reals per block) or |w|^2 (mode 2,
+// one real per block); mode 0 only subtracts.
+template <int MODE, int KC>
+__global__ __launch_bounds__(256) void k_sub_fused(const double* V, double* w, int64_t n, double* partial,
+                                                   const LanczosDev* lz) {
     if (lz->done) return;
-    __shared__ double c[2 * KRYLOV_MAX];
+    constexpr int P = pow2_pairs(KC);
+    __shared__ double c[2 * KC];
     __shared__ double sh[16];
-    __shared__ double sh32[4 * 32];
-    if (threadIdx.x < 2 * KRYLOV_MAX) c[threadIdx.x] = lz->c[threadIdx.x];
+    __shared__ double shp[4 * P];
+    if (threadIdx.x < 2 * KC) c[threadIdx.x] = lz->c[threadIdx.x];
     __syncthreads();
-    double pr[KRYLOV_MAX], pi[KRYLOV_MAX], nrm = 0;
+    double pr[KC], pi[KC], nrm = 0;
 #pragma unroll
-    for (int k = 0; k < KRYLOV_MAX; ++k) pr[k] = pi[k] = 0;
+    for (int k = 0; k < KC; ++k) pr[k] = pi[k] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        double vr[KRYLOV_MAX], vi[KRYLOV_MAX];
+        double vr[KC], vi[KC];
 #pragma unroll
-        for (int k = 0; k < KRYLOV_MAX; ++k) {
-            if (k < kcount) {
-                vr[k] = V[2 * n * k + i];
-                vi[k] = V[2 * n * k + n + i];
-            }
+        for (int k = 0; k < KC; ++k) {
+            vr[k] = V[2 * n * k + i];
+            vi[k] = V[2 * n * k + n + i];
         }
         double wr = w[i], wi = w[i + n];
 #pragma unroll
-        for (int k = 0; k < KRYLOV_MAX; ++k) {
-            if (k < kcount) {
-                const double cr = c[2 * k], ci = c[2 * k + 1];
-                wr -= cr * vr[k] - ci * vi[k];
-                wi -= cr * vi[k] + ci * vr[k];
-            }
+        for (int k = 0; k < KC; ++k) {
+            const double cr = c[2 * k], ci = c[2 * k + 1];
+            wr -= cr * vr[k] - ci * vi[k];
+            wi -= cr * vi[k] + ci * vr[k];
         }
         w[i] = wr;
         w[i + n] = wi;
         if (MODE == 1) {
 #pragma unroll
-            for (int k = 0; k < KRYLOV_MAX; ++k) {
-                if (k < kcount) {
-                    pr[k] += vr[k] * wr + vi[k] * wi;
-                    pi[k] += vr[k] * wi - vi[k] * wr;
-                }
+            for (int k = 0; k < KC; ++k) {
+                pr[k] += vr[k] * wr + vi[k] * wi;
+                pi[k] += vr[k] * wi - vi[k] * wr;
             }
         } else if (MODE == 2) {
             nrm += wr * wr + wi * wi;
         }
     }
     if (MODE == 1) {
-        double a[32];
+        double a[P];
 #pragma unroll
-        for (int k = 0; k < KRYLOV_MAX; ++k) {
-            a[2 * k] = pr[k];
-            a[2 * k + 1] = pi[k];
+        for (int k = 0; k < P / 2; ++k) {
+            a[2 * k] = k < KC ? pr[k] : 0.0;
+            a[2 * k + 1] = k < KC ? pi[k] : 0.0;
         }
-        const double t = block_sum32(a, sh32);
-        if (threadIdx.x < 2 * kcount) partial[blockIdx.x * KRYLOV_MAX * 2 + threadIdx.x] = t;
+        const double t = block_sum_p<P>(a, shp);
+        if (threadIdx.x < 2 * KC) partial[blockIdx.x * 2 * KC + threadIdx.x] = t;
     } else if (MODE == 2) {
         const double a = block_sum(nrm, sh);
         if (threadIdx.x == 0) partial[blockIdx.x] = a;
@@ -365,11 +403,11 @@ __global__ __launch_bounds__(256) void k_lz_iter_small(double* V, int j, int m, 
     }
 }
 
-__global__ void k_lz_beta(const double* partial, int nb, LanczosDev* lz, int j, double tol) {
+__global__ __launch_bounds__(256) void k_lz_beta(const double* partial, int nb, LanczosDev* lz, int j,
+                                                 double tol) {
     if (lz->done) return;
-    double s = 0;
-    for (int i = threadIdx.x; i < nb; i += 64) s += partial[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    __shared__ double sh[16];
+    const double s = block_sum(strided_sum(partial, nb, threadIdx.x, blockDim.x), sh);
     if (threadIdx.x == 0) {
         const double b = sqrt(s);
         const double bprev = j > 0 ? lz->beta[j - 1] : 0.0;
@@ -748,32 +786,65 @@ void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* pa
     hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, x, n, v0, lz, 1, 0, v0f);
 }
 
+// Instantiates a launch for every basis size 1 .. KRYLOV_MAX.
+#define TTN_KC_DISPATCH(kc, LAUNCH)                    \
+    do {                                               \
+        switch (kc) {                                  \
+            case 1: LAUNCH(1); break;                  \
+            case 2: LAUNCH(2); break;                  \
+            case 3: LAUNCH(3); break;                  \
+            case 4: LAUNCH(4); break;                  \
+            case 5: LAUNCH(5); break;                  \
+            case 6: LAUNCH(6); break;                  \
+            case 7: LAUNCH(7); break;                  \
+            case 8: LAUNCH(8); break;                  \
+            case 9: LAUNCH(9); break;                  \
+            case 10: LAUNCH(10); break;                \
+            case 11: LAUNCH(11); break;                \
+            case 12: LAUNCH(12); break;                \
+            case 13: LAUNCH(13); break;                \
+            case 14: LAUNCH(14); break;                \
+            case 15: LAUNCH(15); break;                \
+            case 16: LAUNCH(16); break;                \
+            default: break;                            \
+        }                                              \
+    } while (0)
+static_assert(KRYLOV_MAX == 16, "TTN_KC_DISPATCH covers basis sizes up to 16");
+
 void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
                 LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf) {
     if (g_dry_run) return;
-    hipLaunchKernelGGL(k_multidot_partial, dim3(nb), dim3(RED_THREADS), 0, s, V, kcount, w, n,
-                       partial, lz, wf);
-    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64 * kcount), 0, s, partial, nb, kcount, lz,
-                       alpha_index);
+#define TTN_L(KC) \
+    hipLaunchKernelGGL(k_multidot_partial<KC>, dim3(nb), dim3(RED_THREADS), 0, s, V, w, n, partial, lz, wf)
+    TTN_KC_DISPATCH(kcount, TTN_L);
+#undef TTN_L
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(1024), 0, s, partial, nb, kcount, lz, alpha_index);
 }
 
 void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s) {
     if (g_dry_run) return;
-    hipLaunchKernelGGL(k_sub_fused<0>, dim3(grid_for(n)), dim3(256), 0, s, V, kcount, w, n, (double*)nullptr, lz);
+#define TTN_L(KC) \
+    hipLaunchKernelGGL((k_sub_fused<0, KC>), dim3(grid_for(n)), dim3(256), 0, s, V, w, n, (double*)nullptr, lz)
+    TTN_KC_DISPATCH(kcount, TTN_L);
+#undef TTN_L
 }
 
 void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, double* partial, int nb,
                          LanczosDev* lz, hipStream_t s) {
     if (g_dry_run) return;
-    hipLaunchKernelGGL(k_sub_fused<1>, dim3(nb), dim3(256), 0, s, V, kcount, w, n, partial, lz);
-    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64 * kcount), 0, s, partial, nb, kcount, lz, -1);
+#define TTN_L(KC) hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz)
+    TTN_KC_DISPATCH(kcount, TTN_L);
+#undef TTN_L
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(1024), 0, s, partial, nb, kcount, lz, -1);
 }
 
 void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
                       double* partial, int nb, double tol, hipStream_t s, float* vnextf) {
     if (g_dry_run) return;
-    hipLaunchKernelGGL(k_sub_fused<2>, dim3(nb), dim3(256), 0, s, V, kcount, w, n, partial, lz);
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s, partial, nb, lz, j, tol);
+#define TTN_L(KC) hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz)
+    TTN_KC_DISPATCH(kcount, TTN_L);
+#undef TTN_L
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(256), 0, s, partial, nb, lz, j, tol);
     hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j, vnextf);
 }
 
@@ -781,7 +852,7 @@ void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double*
              double tol, hipStream_t s) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, w, n, partial, &lz->done);
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s, partial, nb, lz, j, tol);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(256), 0, s, partial, nb, lz, j, tol);
     hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j,
                        (float*)nullptr);
 }
