@@ -157,35 +157,82 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_cgemm(Gemm<R> g, int tilesM, i
     }
 }
 
+// Sum of the split-K partials into C (alpha, beta applied).  G threads share
+// an element (G a power of two dividing 256): thread group q sums splits q,
+// q + G, ... with four loads in flight, and the G group sums meet in LDS in a
+// fixed order, so the result does not depend on timing.  Blocks walk
+// (batch, chunk of 256 / G elements) pairs; element indices are 32-bit
+// (the host checks M N < 2^31).
 template <typename R>
-__global__ void k_splitk_reduce(Gemm<R> g, int splits, const R* partial) {
+__global__ __launch_bounds__(256) void k_splitk_reduce(Gemm<R> g, int splits, const R* partial, int G) {
     if (g.skip && *g.skip) return;
-    const int64_t MN = (int64_t)g.M * g.N;
+    __shared__ R sre[256], sim[256];
+    const int MN = g.M * g.N;
     const int nbatch = g.B1 * g.B2;
-    const int64_t total = MN * nbatch;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int b = (int)(e / MN);
-        const int64_t mn = e % MN;
-        const int m = (int)(mn % g.M), n = (int)(mn / g.M);
+    const int epb = 256 / G;
+    const int el = threadIdx.x % epb, grp = threadIdx.x / epb;
+    const int chunks = (MN + epb - 1) / epb;
+    const int64_t sstride = (int64_t)nbatch * 2 * MN;
+    const bool contig = g.scm == 1 && g.scn == g.M;
+    for (int64_t blk = blockIdx.x; blk < (int64_t)chunks * nbatch; blk += gridDim.x) {
+        const int b = (int)(blk / chunks);
+        const int mn = (int)(blk % chunks) * epb + el;
         R re = 0, im = 0;
-        for (int s = 0; s < splits; ++s) {
-            const R* P = partial + ((int64_t)s * nbatch + b) * 2 * MN;
-            re += P[mn];
-            im += P[MN + mn];
+        if (mn < MN) {
+            const R* P = partial + (int64_t)b * 2 * MN + mn;
+            R r4[4] = {0, 0, 0, 0}, i4[4] = {0, 0, 0, 0};
+            int sp = grp;
+            for (; sp + 3 * G < splits; sp += 4 * G) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    r4[u] += P[(int64_t)(sp + u * G) * sstride];
+                    i4[u] += P[(int64_t)(sp + u * G) * sstride + MN];
+                }
+            }
+            for (; sp < splits; sp += G) {
+                r4[0] += P[(int64_t)sp * sstride];
+                i4[0] += P[(int64_t)sp * sstride + MN];
+            }
+            re = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+            im = (i4[0] + i4[1]) + (i4[2] + i4[3]);
         }
-        const int b1 = b % g.B1, b2 = b / g.B1;
-        R* C = g.C + b1 * g.scb1 + b2 * g.scb2;
-        const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
-        re *= g.alpha;
-        im *= g.alpha;
-        if (g.beta) {
-            re += C[off];
-            im += C[off + g.c_plane];
+        if (G > 1) {
+            sre[threadIdx.x] = re;
+            sim[threadIdx.x] = im;
+            __syncthreads();
+            if (grp == 0)
+                for (int q = 1; q < G; ++q) {
+                    re += sre[q * epb + el];
+                    im += sim[q * epb + el];
+                }
+            __syncthreads();
         }
-        C[off] = re;
-        C[off + g.c_plane] = im;
+        if (grp == 0 && mn < MN) {
+            const int b1 = b % g.B1, b2 = b / g.B1;
+            R* C = g.C + b1 * g.scb1 + b2 * g.scb2;
+            const int64_t off = contig ? (int64_t)mn : (int64_t)(mn % g.M) * g.scm + (int64_t)(mn / g.M) * g.scn;
+            re *= g.alpha;
+            im *= g.alpha;
+            if (g.beta) {
+                re += C[off];
+                im += C[off + g.c_plane];
+            }
+            C[off] = re;
+            C[off + g.c_plane] = im;
+        }
     }
+}
+
+// Launch of k_splitk_reduce: up to eight threads per element when the splits
+// are many and the elements few.
+template <typename R>
+void splitk_reduce(const Gemm<R>& g, int splits, const R* partial, hipStream_t s) {
+    const int64_t MN = (int64_t)g.M * g.N, nbatch = (int64_t)g.B1 * g.B2;
+    int G = 1;
+    while (G < 8 && splits >= 8 * 2 * G && MN * nbatch * 2 * G <= 256LL * 1024) G *= 2;
+    const int64_t blocks = (MN + 256 / G - 1) / (256 / G) * nbatch;
+    const int nb = (int)std::min<int64_t>(blocks, 8192);
+    hipLaunchKernelGGL((k_splitk_reduce<R>), dim3(nb), dim3(256), 0, s, g, splits, partial, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -700,7 +747,7 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         // split K until the grid covers the chip once: 256 workgroups of the
         // large tiles (one resident per CU), 512 of the small ones (two per CU)
         const int64_t target = big ? 256 : 512;
-        if (tiles < 256 && ktiles >= 8) {
+        if (tiles < 256 && ktiles >= 8 && (int64_t)g.M * g.N < (1LL << 31)) {
             splits = (int)std::min<int64_t>((target + tiles - 1) / tiles, ktiles / 4);
             const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
             const int64_t cap = per > 0 ? ws.bytes / per : 1;
@@ -781,9 +828,7 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
 #undef TTN_BF16_LAUNCH
         if (ev1) (void)hipEventRecord(ev1, s);
         if (splits > 1) {
-            const int64_t total = (int64_t)g.M * g.N * nbatch;
-            const int nb = (int)std::min<int64_t>((total + 255) / 256, 4096);
-            hipLaunchKernelGGL((k_splitk_reduce<R>), dim3(nb), dim3(256), 0, s, g, splits, (const R*)ws.partial);
+            splitk_reduce(g, splits, (const R*)ws.partial, s);
         }
         return true;
     }
@@ -791,7 +836,7 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
     const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
     const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
     int splits = 1;
-    if (K > 0 && tiles < 256 && K > 8 * BK) {
+    if (K > 0 && tiles < 256 && K > 8 * BK && (int64_t)g.M * g.N < (1LL << 31)) {
         splits = (int)std::min<int64_t>((512 + tiles - 1) / tiles, K / (4 * BK));
         const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
         const int64_t cap = per > 0 ? ws.bytes / per : 1;
@@ -812,10 +857,7 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
                        tilesM, tilesN, splits, kchunk, (R*)ws.partial, a_mfast, b_nfast);
     if (ev1) (void)hipEventRecord(ev1, s);
     if (splits > 1) {
-        const int64_t total = (int64_t)g.M * g.N * nbatch;
-        const int nb = (int)std::min<int64_t>((total + 255) / 256, 4096);
-        hipLaunchKernelGGL((k_splitk_reduce<R>), dim3(nb), dim3(256), 0, s, g, splits,
-                           (const R*)ws.partial);
+        splitk_reduce(g, splits, (const R*)ws.partial, s);
     }
     return true;
 }
