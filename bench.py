@@ -192,14 +192,15 @@ def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True):
     return g, (t1 - t0) * 1e3 / steps, prof, ms_prof, F, n2, E
 
 
-def run_adjoint(w, steps):
-    """Forward + adjoint: `steps` recorded steps (checkpoint every 10) and the
-    backward pass of the GHZ fidelity gradient, timed separately."""
+def run_adjoint(w, steps, ckpt=10):
+    """Forward + adjoint: `steps` recorded steps (a state checkpoint every
+    `ckpt` steps) and the backward pass of the GHZ fidelity gradient, timed
+    separately."""
     import torch
     from paper_2210_03763_amd import ttn
     g = ttn.TTN(w, device="cuda:0")
     g.step(1)
-    nbytes = g.record(steps, 10)
+    nbytes = g.record(steps, ckpt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.step(steps)
@@ -212,7 +213,7 @@ def run_adjoint(w, steps):
     del g
     torch.cuda.empty_cache()
     fwd, bwd = (t1 - t0) / steps, (t2 - t1) / steps
-    return {"steps": steps, "fwd_ms_per_step": round(1e3 * fwd, 2), "bwd_ms_per_step": round(1e3 * bwd, 2),
+    return {"steps": steps, "ckpt_every": ckpt, "fwd_ms_per_step": round(1e3 * fwd, 2), "bwd_ms_per_step": round(1e3 * bwd, 2),
             "fwd_adj_steps_per_s": round(1.0 / (fwd + bwd), 4), "adjoint_buffer_gib": round(nbytes / 2 ** 30, 2),
             "max_abs_grad": float(max(abs(go).max(), abs(gd).max()))}
 
@@ -407,8 +408,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
-    ap.add_argument("--adjoint-steps", type=int, default=2,
+    ap.add_argument("--adjoint-steps", type=int, default=6,
                     help="recorded steps of the forward+adjoint measurement (0: skip)")
+    ap.add_argument("--adjoint-ckpt", type=int, default=1,
+                    help="state checkpoint interval of the forward+adjoint measurement")
     ap.add_argument("--sample-shots", type=int, default=1000000,
                     help="projective-measurement shots of the sampling measurement (0: skip)")
     ap.add_argument("--open-gamma", type=float, default=0.02,
@@ -488,9 +491,9 @@ def main():
     gm.close()
     if args.adjoint_steps > 0:
         print(f"[bench] forward+adjoint: {args.adjoint_steps} recorded steps", file=sys.stderr, flush=True)
-        adj = {"mixed": run_adjoint(w, args.adjoint_steps)}
+        adj = {"mixed": run_adjoint(w, args.adjoint_steps, args.adjoint_ckpt)}
         if not args.no_fp64 and w.precision == ttn.PREC_FP32:
-            adj["fp64"] = run_adjoint(w.copy(precision=ttn.PREC_FP64), args.adjoint_steps)
+            adj["fp64"] = run_adjoint(w.copy(precision=ttn.PREC_FP64), args.adjoint_steps, args.adjoint_ckpt)
             adj["mixed_speedup_fwd_adj"] = round(adj["fp64"]["fwd_ms_per_step"] + adj["fp64"]["bwd_ms_per_step"], 2) / \
                 max(1e-9, adj["mixed"]["fwd_ms_per_step"] + adj["mixed"]["bwd_ms_per_step"])
             adj["mixed_speedup_fwd_adj"] = round(adj["mixed_speedup_fwd_adj"], 3)
