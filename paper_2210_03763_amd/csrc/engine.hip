@@ -736,14 +736,20 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
         }
         return;
     }
+    // operators of at most LZ_FUSE_NB reduction blocks take the totals of each
+    // pass inside the following kernel
+    const bool fuse = nb <= LZ_FUSE_NB;
+    static_assert((int64_t)RED_BLOCKS * KRYLOV_MAX * 2 >= 2 * LZ_PARTIAL_HALF, "reduction buffer too small");
     for (int j = 0; j < h->m; ++j) {
         double* vj = h->Vk + 2 * n * j;
         apply_op_prec(h, o, vj, h->W, &lz->done, false, xf != nullptr);
         // classical Gram-Schmidt, two passes: the first projection also gives alpha_j
-        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s, xf ? h->Yf : nullptr);
-        if (j == h->m - 1) break;
-        lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s);
-        lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s, xf);
+        const bool last = j == h->m - 1;
+        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s, xf ? h->Yf : nullptr, last || !fuse);
+        if (last) break;
+        lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s, fuse);
+        lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s, xf,
+                         fuse);
     }
 }
 

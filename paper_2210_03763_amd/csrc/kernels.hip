@@ -144,6 +144,37 @@ __global__ void k_scale_by(const double* x, int64_t n, double* y, const LanczosD
     }
 }
 
+// v_{j+1} = w / beta_j with beta_j totalled by every block from the nb
+// norm partials of k_sub_fused<2> and the breakdown test of k_lz_beta taken
+// alike in every block (block 0 records beta_j, or the breakdown); also the
+// FP32 copy yf when yf != nullptr.
+__global__ __launch_bounds__(256) void k_scale_next(const double* x, int64_t n, double* y, LanczosDev* lz,
+                                                  const double* pnorm, int nb, int j, double tol, float* yf) {
+    if (lz->done) return;
+    __shared__ double sh[16];
+    __shared__ double s_b;
+    const double t = block_sum(strided_sum(pnorm, nb, threadIdx.x, blockDim.x), sh);
+    if (threadIdx.x == 0) s_b = sqrt(t);
+    __syncthreads();
+    const double b = s_b;
+    const double bprev = j > 0 ? lz->beta[j - 1] : 0.0;
+    const bool stop = !(b > tol * (fabs(lz->alpha[j]) + bprev));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (stop)
+            lz->done = 1;
+        else
+            lz->beta[j] = b;
+    }
+    if (stop) return;
+    const double inv = 1.0 / b;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = x[i] * inv;
+        y[i] = v;
+        if (yf) yf[i] = (float)v;
+    }
+}
+
 // partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < KC (2 KC reals per
 // block); with wf != nullptr w is first widened from the FP32 matvec output
 // wf (and stored).  KC is a template argument so that the per-thread arrays
@@ -191,6 +222,56 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* V, const
     if (threadIdx.x < 2 * KC) partial[blockIdx.x * 2 * KC + threadIdx.x] = t;
 }
 
+// Records the projections tot[2k], tot[2k + 1] (k < kcount) of one
+// Gram-Schmidt pass in the Lanczos state; called by thread k of one block.
+// alpha_index >= 0 marks the first pass of iteration alpha_index (alpha_j,
+// and for an Arnoldi basis the Hessenberg column), -1 the second pass (its
+// projections are added to the Hessenberg column).
+__device__ inline void lz_record_projection(LanczosDev* lz, const double* tot, int kcount, int alpha_index,
+                                            int k) {
+    const double re = tot[2 * k], im = tot[2 * k + 1];
+    lz->c[2 * k] = re;
+    lz->c[2 * k + 1] = im;
+    if (k == alpha_index) {
+        lz->alpha[k] = re;
+        lz->m_eff = k + 1;
+    }
+    if (lz->nonherm) {
+        double* hp = lz->hs + 2 * ((kcount - 1) * KRYLOV_MAX + k);
+        if (alpha_index >= 0) {
+            hp[0] = re;
+            hp[1] = im;
+        } else {
+            hp[0] += re;
+            hp[1] += im;
+        }
+    }
+}
+
+// Totals of the nv <= 32 reals per block of nb block partials (layout
+// [block][nv]) into out[0..nv), in an order that does not depend on the
+// calling block; 256 threads, sh holds 256 doubles.
+__device__ inline void block_partials_total(const double* p, int nb, int nv, double* sh, double* out) {
+    const int v = threadIdx.x & 31, g = threadIdx.x >> 5, ng = blockDim.x >> 5;
+    double u[4] = {0, 0, 0, 0};
+    if (v < nv) {
+        int b = g;
+        for (; b + 3 * ng < nb; b += 4 * ng) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u[q] += p[(int64_t)(b + q * ng) * nv + v];
+        }
+        for (; b < nb; b += ng) u[0] += p[(int64_t)b * nv + v];
+    }
+    sh[32 * g + v] = (u[0] + u[1]) + (u[2] + u[3]);
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        double r = 0;
+        for (int q = 0; q < ng; ++q) r += sh[32 * q + threadIdx.x];
+        out[threadIdx.x] = r;
+    }
+    __syncthreads();
+}
+
 // Totals of the 2 kcount reals per block (layout of k_multidot_partial) into
 // the Lanczos state.  1024 threads: thread (g, v) = (t / 32, t % 32) sums value
 // v of blocks g, g + 32, ..., so that each step of the 32 groups reads one
@@ -223,40 +304,32 @@ __global__ __launch_bounds__(1024) void k_multidot_final(const double* partial, 
     __syncthreads();
     const int k = threadIdx.x;
     if (k >= kcount) return;
-    const double re = tot[2 * k], im = tot[2 * k + 1];
-    lz->c[2 * k] = re;
-    lz->c[2 * k + 1] = im;
-    if (k == alpha_index) {
-        lz->alpha[k] = re;
-        lz->m_eff = k + 1;
-    }
-    if (lz->nonherm) {
-        // Hessenberg column kcount - 1: the first pass (alpha_index >= 0)
-        // sets it, the second Gram-Schmidt pass adds its projections
-        double* hp = lz->hs + 2 * ((kcount - 1) * KRYLOV_MAX + k);
-        if (alpha_index >= 0) {
-            hp[0] = re;
-            hp[1] = im;
-        } else {
-            hp[0] += re;
-            hp[1] += im;
-        }
-    }
+    lz_record_projection(lz, tot, kcount, alpha_index, k);
 }
 
 // w -= sum_k c_k V_k; then, per block, partial sums of either the new
 // projections conj(V_k) w (mode 1, 2 KC reals per block) or |w|^2 (mode 2,
-// one real per block); mode 0 only subtracts.
+// one real per block); mode 0 only subtracts.  The coefficients c come from
+// the Lanczos state, or, with pin != nullptr, every block totals them from
+// the previous pass's nbin block partials itself (the same sums in every
+// block) and block 0 records them in the state (alpha_index as in
+// lz_record_projection); pin must not alias partial.
 template <int MODE, int KC>
 __global__ __launch_bounds__(256) void k_sub_fused(const double* V, double* w, int64_t n, double* partial,
-                                                   const LanczosDev* lz) {
+                                                   LanczosDev* lz, const double* pin, int nbin, int alpha_index) {
     if (lz->done) return;
     constexpr int P = pow2_pairs(KC);
-    __shared__ double c[2 * KC];
+    __shared__ double c[32];
     __shared__ double sh[16];
     __shared__ double shp[4 * P];
-    if (threadIdx.x < 2 * KC) c[threadIdx.x] = lz->c[threadIdx.x];
-    __syncthreads();
+    __shared__ double shq[256];
+    if (pin) {
+        block_partials_total(pin, nbin, 2 * KC, shq, c);
+        if (blockIdx.x == 0 && threadIdx.x < KC) lz_record_projection(lz, c, KC, alpha_index, threadIdx.x);
+    } else {
+        if (threadIdx.x < 2 * KC) c[threadIdx.x] = lz->c[threadIdx.x];
+        __syncthreads();
+    }
     double pr[KC], pi[KC], nrm = 0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) pr[k] = pi[k] = 0;
@@ -812,36 +885,65 @@ void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* pa
 static_assert(KRYLOV_MAX == 16, "TTN_KC_DISPATCH covers basis sizes up to 16");
 
 void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
-                LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf) {
+                LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf, bool total) {
     if (g_dry_run) return;
 #define TTN_L(KC) \
     hipLaunchKernelGGL(k_multidot_partial<KC>, dim3(nb), dim3(RED_THREADS), 0, s, V, w, n, partial, lz, wf)
     TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
-    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(1024), 0, s, partial, nb, kcount, lz, alpha_index);
+    if (total)
+        hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(1024), 0, s, partial, nb, kcount, lz, alpha_index);
 }
 
 void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s) {
     if (g_dry_run) return;
-#define TTN_L(KC) \
-    hipLaunchKernelGGL((k_sub_fused<0, KC>), dim3(grid_for(n)), dim3(256), 0, s, V, w, n, (double*)nullptr, lz)
+#define TTN_L(KC)                                                                                              \
+    hipLaunchKernelGGL((k_sub_fused<0, KC>), dim3(grid_for(n)), dim3(256), 0, s, V, w, n, (double*)nullptr, lz, \
+                       (const double*)nullptr, 0, 0)
     TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
 }
 
+// With fuse (nb <= LZ_FUSE_NB) the totals of the first pass are taken inside
+// k_sub_fused<1> from the partials lz_project left at `partial`, and its own
+// partials go to partial + LZ_PARTIAL_HALF.
 void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, double* partial, int nb,
-                         LanczosDev* lz, hipStream_t s) {
+                         LanczosDev* lz, hipStream_t s, bool fuse) {
     if (g_dry_run) return;
-#define TTN_L(KC) hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz)
+    if (fuse) {
+#define TTN_L(KC)                                                                                             \
+    hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial + LZ_PARTIAL_HALF, lz, \
+                       (const double*)partial, nb, kcount - 1)
+        TTN_KC_DISPATCH(kcount, TTN_L);
+#undef TTN_L
+        return;
+    }
+#define TTN_L(KC)                                                                                         \
+    hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz, \
+                       (const double*)nullptr, 0, 0)
     TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
     hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(1024), 0, s, partial, nb, kcount, lz, -1);
 }
 
+// With fuse the second pass's totals are taken inside k_sub_fused<2> from
+// partial + LZ_PARTIAL_HALF, and beta_j inside the scaling kernel.
 void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
-                      double* partial, int nb, double tol, hipStream_t s, float* vnextf) {
+                      double* partial, int nb, double tol, hipStream_t s, float* vnextf, bool fuse) {
     if (g_dry_run) return;
-#define TTN_L(KC) hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz)
+    if (fuse) {
+#define TTN_L(KC)                                                                                              \
+    hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz,                  \
+                       (const double*)(partial + LZ_PARTIAL_HALF), nb, -1)
+        TTN_KC_DISPATCH(kcount, TTN_L);
+#undef TTN_L
+        hipLaunchKernelGGL(k_scale_next, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz,
+                           (const double*)partial, nb, j, tol, vnextf);
+        return;
+    }
+#define TTN_L(KC)                                                                                         \
+    hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz, \
+                       (const double*)nullptr, 0, 0)
     TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(256), 0, s, partial, nb, lz, j, tol);

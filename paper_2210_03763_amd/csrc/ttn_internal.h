@@ -93,16 +93,25 @@ void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_
 // v0f != nullptr also receives v0 in FP32 (the next mixed matvec's input)
 void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
               hipStream_t s, int nonherm = 0, float* v0f = nullptr);
-// wf != nullptr: w is first written from the FP32 matvec output wf (widened)
+// Reductions over at most LZ_FUSE_NB blocks may take their totals inside the
+// next kernel of the iteration (every block sums the block partials itself),
+// which saves the one-block total kernels; their partials alternate between
+// `partial` and partial + LZ_PARTIAL_HALF (the reduction buffer holds both).
+constexpr int LZ_FUSE_NB = 256;
+constexpr int64_t LZ_PARTIAL_HALF = (int64_t)LZ_FUSE_NB * 2 * KRYLOV_MAX;
+// wf != nullptr: w is first written from the FP32 matvec output wf (widened);
+// total = false leaves the projections as block partials for a fused
+// lz_subtract_project
 void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
-                LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf = nullptr);
+                LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf = nullptr, bool total = true);
 void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s);
 // w -= V c, then c <- V^H w (second Gram-Schmidt pass), fused
 void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, double* partial, int nb,
-                         LanczosDev* lz, hipStream_t s);
+                         LanczosDev* lz, hipStream_t s, bool fuse = false);
 // w -= V c, then beta_j = ||w||, breakdown test, v_{j+1} = w / beta_j
 void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
-                      double* partial, int nb, double tol, hipStream_t s, float* vnextf = nullptr);
+                      double* partial, int nb, double tol, hipStream_t s, float* vnextf = nullptr,
+                      bool fuse = false);
 void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
              double tol, hipStream_t s);
 // a whole iteration after the matvec (projection, two Gram-Schmidt passes,
