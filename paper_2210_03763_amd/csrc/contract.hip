@@ -223,11 +223,54 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(Gemm<R> g, int splits, co
     }
 }
 
-// Launch of k_splitk_reduce: up to eight threads per element when the splits
-// are many and the elements few.
+// k_splitk_reduce for a contiguous, 16-byte aligned output with few splits:
+// each thread sums one 16-byte vector of W consecutive elements of every
+// split (in split order, as the scalar kernel does with one thread per
+// element) and stores it whole.
+template <typename R>
+__global__ __launch_bounds__(256) void k_splitk_reduce_vec(Gemm<R> g, int splits, const R* partial) {
+    if (g.skip && *g.skip) return;
+    constexpr int W = 16 / sizeof(R);
+    typedef R V __attribute__((ext_vector_type(W)));
+    const int MN = g.M * g.N, nbatch = g.B1 * g.B2;
+    const int nv = MN / W;
+    const int64_t sstride = (int64_t)nbatch * 2 * MN;
+    const int total = nv * nbatch;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int b = e / nv, q = e - b * nv;
+        const R* P = partial + (int64_t)b * 2 * MN + (int64_t)q * W;
+        V re = *(const V*)P, im = *(const V*)(P + MN);
+        for (int sp = 1; sp < splits; ++sp) {
+            re += *(const V*)(P + sp * sstride);
+            im += *(const V*)(P + sp * sstride + MN);
+        }
+        const int b1 = b % g.B1, b2 = b / g.B1;
+        R* C = g.C + b1 * g.scb1 + b2 * g.scb2 + (int64_t)q * W;
+        re *= g.alpha;
+        im *= g.alpha;
+        if (g.beta) {
+            re += *(const V*)C;
+            im += *(const V*)(C + g.c_plane);
+        }
+        *(V*)C = re;
+        *(V*)(C + g.c_plane) = im;
+    }
+}
+
+// Launch of the split-K reduction: the vector kernel for contiguous aligned
+// outputs and fewer than four splits, else k_splitk_reduce with up to eight
+// threads per element when the splits are many and the elements few.
 template <typename R>
 void splitk_reduce(const Gemm<R>& g, int splits, const R* partial, hipStream_t s) {
     const int64_t MN = (int64_t)g.M * g.N, nbatch = (int64_t)g.B1 * g.B2;
+    constexpr int W = 16 / sizeof(R);
+    const bool contig = g.scm == 1 && g.scn == g.M;
+    if (splits < 4 && contig && MN % W == 0 && MN * nbatch / W < (1LL << 31) && (uintptr_t)g.C % 16 == 0 &&
+        (uintptr_t)partial % 16 == 0 && g.c_plane % W == 0 && g.scb1 % W == 0 && g.scb2 % W == 0) {
+        const int nb = (int)std::min<int64_t>((MN * nbatch / W + 255) / 256, 8192);
+        hipLaunchKernelGGL((k_splitk_reduce_vec<R>), dim3(nb), dim3(256), 0, s, g, splits, partial);
+        return;
+    }
     int G = 1;
     while (G < 8 && splits >= 8 * 2 * G && MN * nbatch * 2 * G <= 256LL * 1024) G *= 2;
     const int64_t blocks = (MN + 256 / G - 1) / (256 / G) * nbatch;
