@@ -431,7 +431,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the TDVP sweep is sequential "
-              f"over tree nodes and this build has no multi-GPU path", file=sys.stderr, flush=True)
+              f"over tree nodes and the library has no multi-GPU path", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import torch
