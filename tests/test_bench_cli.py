@@ -26,3 +26,25 @@ def test_heff_flops_and_sampling_flops():
     assert 2.6e13 < fps < 2.9e13
     # per shot: two batch GEMMs (16 D_L D_R D_P real flops) per node above the bottom
     assert 4.0e8 < bench.sample_flops_per_shot(w) < 5.5e8
+
+
+def test_traffic_summary_tracks_the_contraction_source(tmp_path, monkeypatch):
+    """roofline.traffic comes from the committed counter summary only while
+    the contraction source still has the hash recorded there and the workload
+    matches; otherwise it is null."""
+    import bench
+    src = tmp_path / "contract.hip"
+    src.write_bytes(b"// kernel source\n")
+    import hashlib
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    summary = tmp_path / "traffic.md"
+    summary.write_text(f"- workload: W1\n- contract_source_sha256: `{sha}`\n- hbm_bytes_per_launch: 123456\n")
+    monkeypatch.setattr(bench, "CONTRACT_SRC", str(src))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(summary))
+    assert bench.measured_traffic("W1") == 123456.0
+    assert bench.measured_traffic("W2") is None
+    src.write_bytes(b"// kernel source, changed\n")
+    assert bench.measured_traffic("W1") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.md"))
+    assert bench.measured_traffic("W1") is None
+
