@@ -330,11 +330,14 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, 
     static_assert(QA >= 1 && QB >= 1, "tile smaller than the block");
     typedef typename MfmaT<R>::acc_t acc_t;
     // LDS tiles [buffer][plane][row][col]: an operand whose global layout is
-    // contiguous along k is staged k-contiguous with an odd row stride
-    // (BK + 1), so that both the coalesced stash and the MFMA fragment reads
-    // hit distinct banks; the others are staged [k][index] with a pad.
-    constexpr int AR = AK ? BM : BK, AC = AK ? BK + 1 : BM + PAD;
-    constexpr int BR = BKF ? BN : BK, BC = BKF ? BK + 1 : BN + PAD;
+    // contiguous along k is staged k-contiguous with a row stride of BK + 1
+    // (BK + 2 for 32-wide FP32 k-tiles: a fragment read takes rows r = 0..15
+    // at k + q, q = 0..3, and 34 r + q, unlike 33 r + q, spreads over 64
+    // distinct banks), so that both the coalesced stash and the MFMA fragment
+    // reads hit distinct banks; the others are staged [k][index] with a pad.
+    constexpr int KS = BK + ((sizeof(R) == 4 && BK == 32) ? 2 : 1);
+    constexpr int AR = AK ? BM : BK, AC = AK ? KS : BM + PAD;
+    constexpr int BR = BKF ? BN : BK, BC = BKF ? KS : BN + PAD;
     __shared__ R As[2][2][AR][AC];
     __shared__ R Bs[2][2][BR][BC];
     int64_t bid = blockIdx.x;
