@@ -366,6 +366,7 @@ class OracleTTN:
         self.omx_t = torch.zeros(n_sites, dtype=RDT)
         self.omz_t = torch.zeros(n_sites, dtype=RDT)
         self.stats = []
+        self.qr_min = math.inf
 
     # -- initial state --------------------------------------------------
     def init_product(self, init_product, eps=0.0, noise=None):
@@ -564,10 +565,18 @@ class OracleTTN:
         return out
 
     # -- sweeps ----------------------------------------------------------
+    def _qr(self, T, leg):
+        """Gauge-move QR (qr_toward) that also keeps the smallest R_kk seen
+        since the last reset of qr_min: the conditioning of the step's gauge
+        moves (a diagnostic; it changes no arithmetic)."""
+        Q, R = qr_toward(T, leg)
+        self.qr_min = min(self.qr_min, float(torch.diagonal(R).real.min()))
+        return Q, R
+
     def _visit_fwd(self, v, tau):
         tr = self.tree
         u, leg = tr.parent[v], tr.leg_in_parent(v)
-        Q, R = qr_toward(self.T[u], leg)
+        Q, R = self._qr(self.T[u], leg)
         self.T[u] = Q
         self.T[v] = on_P(R, self.T[v])          # absorb C = R^T below
         self.build_down(v)
@@ -575,7 +584,7 @@ class OracleTTN:
             for c in tr.children[v]:
                 self._visit_fwd(c, tau)
         self.evolve_node(v, tau)
-        Q, R = qr_toward(self.T[v], 2)
+        Q, R = self._qr(self.T[v], 2)
         self.T[v] = Q
         self.build_up(v)
         C = self.evolve_bond(v, R, tau)
@@ -584,7 +593,7 @@ class OracleTTN:
     def _visit_bwd(self, v, tau):
         tr = self.tree
         u, leg = tr.parent[v], tr.leg_in_parent(v)
-        Q, R = qr_toward(self.T[u], leg)
+        Q, R = self._qr(self.T[u], leg)
         self.T[u] = Q
         self.build_down(v)
         C = self.evolve_bond(v, R.t(), tau)
@@ -593,7 +602,7 @@ class OracleTTN:
         if not tr.is_bottom(v):
             for c in reversed(tr.children[v]):
                 self._visit_bwd(c, tau)
-        Q, R = qr_toward(self.T[v], 2)
+        Q, R = self._qr(self.T[v], 2)
         self.T[v] = Q
         self.build_up(v)
         self.T[u] = on_leg(leg, R, self.T[u])
@@ -741,10 +750,11 @@ def run(w, n_steps: Optional[int] = None, st: Optional[OracleTTN] = None, step0:
                 st.apply_gate(s, U)
         st.set_time(edges, om, de, (n + 0.5) * w.dt, getattr(w, "omega_x", None), getattr(w, "omega_z", None))
         st.rebuild_up()
+        st.qr_min = math.inf
         st.sweep_fwd(tau)
         st.sweep_bwd(tau)
         if record:
-            rec = dict(step=n, norm2=st.norm2(), energy=st.energy())
+            rec = dict(step=n, norm2=st.norm2(), energy=st.energy(), min_r_diag=st.qr_min)
             if st.gamma != 0.0:
                 rec["rydberg_population"] = st.rydberg_population()
             recs.append(rec)

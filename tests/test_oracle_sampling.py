@@ -8,9 +8,13 @@
     at maximal bond dimension (a chi-square statistic far below its failure
     threshold for the fixed seed) -- pins that the draws follow |psi|^2,
     i.e. the column mixture and the conditional states.
-  * The generator: mean and bin counts of uniforms, and distinct outputs for
-    distinct counters (Philox is a bijection of the counter for a fixed key).
+  * The generator: the published Philox4x32-10 known-answer vectors
+    (tests/golden/philox4x32_10_kat.txt; a wrong multiplier, Weyl constant,
+    round count or output permutation fails them), mean and bin counts of
+    uniforms, and distinct outputs for distinct counters (Philox is a
+    bijection of the counter for a fixed key).
 """
+import os
 import math
 
 import numpy as np
@@ -25,6 +29,21 @@ from paper_2210_03763_amd import workload as W
 def _evolved(w, n_steps):
     st, _ = O.run(w, n_steps=n_steps, record=False)
     return st
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_philox_known_answer_vectors():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x, 16) for x in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        out = S.philox4x32_10(np.array([r[:4]], dtype=np.uint64), (r[4], r[5]))
+        assert [int(x) for x in out[0]] == r[6:], (r, out)
 
 
 def test_generator_uniformity_and_bijectivity():
