@@ -37,7 +37,7 @@ if ROOT not in sys.path:
 METRIC = "TDVP steps/sec + H_eff MFMA util, 8x8 chi=128; mixed vs FP64 at 1e-5 fidel"
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 CONTRACT_SRC = os.path.join(ROOT, "paper_2210_03763_amd", "csrc", "contract.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_f32_8x8_d4_chi128_mixed_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heff_contract_f32_8x8_d4_chi128_mixed_hbm_traffic.md")
 
 
 def measured_traffic(workload_name: str):
@@ -57,18 +57,9 @@ def measured_traffic(workload_name: str):
     if kv.get("contract_source_sha256") != sha or kv.get("workload") != workload_name:
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_heff_launch"])
     except (KeyError, ValueError):
         return None
-
-
-class KernelProf(C.Structure):
-    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double)]
-
-
-class Profile(C.Structure):
-    _fields_ = [("gemm_f32", KernelProf), ("gemm_f64", KernelProf), ("heff", KernelProf),
-                ("matvecs", C.c_int64)]
 
 
 def heff_flops_per_step(w) -> float:
@@ -98,6 +89,29 @@ def heff_flops_per_step(w) -> float:
             bond = dp * dp * (dp * (1 + 2 * s) + dp * (1 + 2 * s))
             total += nn * 2 * m * bond
     return 8.0 * total
+
+
+def host_cpu() -> dict:
+    """The host the oracle ran on: logical CPUs of the machine, CPUs this
+    process may use, CPU model, and the BLAS/threading torch uses."""
+    import torch
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    cfg = torch.__config__.show()
+    blas = "MKL" if "BLAS_INFO=mkl" in cfg or "USE_MKL=ON" in cfg else (
+        "OpenBLAS" if "openblas" in cfg.lower() else "unknown")
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model,
+            "torch_threads": torch.get_num_threads(), "blas": blas}
 
 
 def cpu_baseline(w, flops_per_step, budget_s=30.0):
@@ -131,6 +145,7 @@ def cpu_baseline(w, flops_per_step, budget_s=30.0):
             break
     rate = n_done * fl / el
     return {"value": rate / flops_per_step, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"{n_done} oracle H_eff matvecs of the level-{tr.level[v]} node "
                       f"({DL}x{DR}x{DP}, {fl / 1e9:.0f} GFLOP each) in {el:.1f} s on CPU "
                       f"({rate / 1e9:.1f} GFLOP/s), scaled by {flops_per_step / 1e12:.1f} TFLOP of "
@@ -152,16 +167,14 @@ def calibration_copy(mib):
           flush=True)
 
 
-def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True):
+def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True, launch_log=None):
     """Warm-up steps (the first captures the step graph), `steps` timed steps
     replayed from the graph, then -- with profile -- `steps` more steps in a
     profiling window (launched eagerly, each contraction bracketed by HIP
-    events on the handle's stream)."""
+    events on the handle's stream; launch_log receives the window's launch
+    records as JSON)."""
     import torch
     from paper_2210_03763_amd import ttn
-    L = ttn.lib()
-    L.ttn_profile_begin.argtypes = [C.c_void_p]
-    L.ttn_profile_end.argtypes = [C.c_void_p, C.POINTER(Profile)]
     g = ttn.TTN(w, device="cuda:0")
     if not graphs:
         g.set_graphs(False)
@@ -174,18 +187,21 @@ def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     print(f"[bench] {steps} timed step(s) done", file=sys.stderr, flush=True)
-    prof = Profile()
+    prof = ttn.Profile()
     ms_prof = None
     if profile:
         if calib_mib > 0:
             calibration_copy(calib_mib)
-        assert L.ttn_profile_begin(g.h) == 0
+        g.profile_begin()
         t2 = time.perf_counter()
         g.step(steps)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        assert L.ttn_profile_end(g.h, C.byref(prof)) == 0
+        prof = g.profile_end()
         ms_prof = (t3 - t2) * 1e3 / steps
+        if launch_log:
+            with open(launch_log, "w") as f:
+                json.dump({"workload": w.name, "steps": steps, "launches": g.profile_launches()}, f)
         print(f"[bench] {steps} profiled step(s) done", file=sys.stderr, flush=True)
     F, _ = g.fidelity()
     n2, E = g.observables()
@@ -420,6 +436,8 @@ def main():
                     help="launch every step eagerly (for counter collection; kernels are the same)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--launch-log", default=None,
+                    help="write the profiling window's contraction launch records (JSON) here")
     ap.add_argument("--bf16-steps", type=int, default=2,
                     help="also time the BF16x3 precision mode over this many steps")
     ap.add_argument("--c5-steps", type=int, default=0,
@@ -448,20 +466,27 @@ def main():
     print(f"[bench] mixed run: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr, flush=True)
     gm, ms_mixed, prof, ms_prof, F_m, n2_m, E_m = run_gpu(w, args.steps, args.warmup,
                                                           calib_mib=args.calib_copy_mib,
-                                                          graphs=not args.no_graphs)
+                                                          graphs=not args.no_graphs,
+                                                          launch_log=args.launch_log)
     print(f"[bench] mixed {ms_mixed:.1f} ms/step F={F_m:.12f}", file=sys.stderr, flush=True)
-    k = prof.gemm_f32 if w.precision == ttn.PREC_FP32 else prof.gemm_f64
     dt = "fp32" if w.precision == ttn.PREC_FP32 else "fp64"
+    kall = prof.gemm_f32 if w.precision == ttn.PREC_FP32 else prof.gemm_f64
+    k = prof.heff          # the H_eff / K_eff matvec launches: the metric's kernel
     avg_ms = k.ms / max(1, k.launches)
     achieved = (k.flops / 1e12) / (k.ms / 1e3) if k.ms > 0 else 0.0
+    ach_all = (kall.flops / 1e12) / (kall.ms / 1e3) if kall.ms > 0 else 0.0
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS[dt], 4),
             "traffic": measured_traffic(w.name) if dt == "fp32" else None,
-            "kernel": f"complex {dt.upper()} contraction launches (k_cgemm_mfma / k_cgemm + split-K "
-                      f"reduction): H_eff/K_eff stages and environment updates",
+            "kernel": f"H_eff/K_eff matvec launches of the complex {dt.upper()} contraction kernel "
+                      f"(k_cgemm_mfma / k_cgemm, each timed with its split-K reduction)",
             "launches": int(k.launches), "avg_launch_ms": round(avg_ms, 5),
             "algorithmic_gflop_per_launch": round(k.flops / max(1, k.launches) / 1e9, 4),
-            "heff_share_of_kernel_flops": round(prof.heff.flops / max(1.0, k.flops), 4),
+            "matvecs": int(prof.matvecs),
+            "all_contractions": {"launches": int(kall.launches), "achieved": round(ach_all, 3),
+                                 "frac": round(ach_all / PEAK_TFLOPS[dt], 4),
+                                 "avg_launch_ms": round(kall.ms / max(1, kall.launches), 5),
+                                 "heff_share_of_flops": round(k.flops / max(1.0, kall.flops), 4)},
             "window": f"the {args.steps} steps after the timed ones, launched eagerly inside a profiling "
                       f"window ({ms_prof:.1f} ms/step there); kernel durations do not depend on graph replay"}
     out = {"metric": METRIC, "value": round(1e3 / ms_mixed, 4), "unit": "steps/s", "n_gpus": 1,

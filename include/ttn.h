@@ -256,25 +256,47 @@ typedef struct {
 } ttn_kernel_prof;
 
 typedef struct {
-    ttn_kernel_prof gemm_f32;   /* complex FP32 contraction kernel               */
+    ttn_kernel_prof gemm_f32;   /* complex FP32 contraction kernel (incl. BF16x3) */
     ttn_kernel_prof gemm_f64;   /* complex FP64 contraction kernel               */
     ttn_kernel_prof heff;       /* the subset that applies H_eff / K_eff         */
     int64_t matvecs;            /* H_eff / K_eff applications                     */
+    ttn_kernel_prof gemm_bf16x3; /* the FP32 launches that ran the BF16x3 kernel  */
 } ttn_profile;
 
+/* One contraction launch of a profiling window, in launch order. */
+typedef struct {
+    int32_t kernel;   /* 1 VALU tile kernel (k_cgemm), 2 MFMA kernel
+                         (k_cgemm_mfma), 3 BF16x3 kernel (k_cgemm_bf16x3)     */
+    int32_t prec;     /* 0 FP64 operands, 1 FP32 operands                     */
+    int32_t heff;     /* 1 when the launch applies H_eff / K_eff              */
+    int32_t splits;   /* split-K factor; > 1: a k_splitk_reduce* launch follows
+                         the main kernel and is timed with it                 */
+    double flops;     /* algorithmic real flops (8 M N K)                     */
+    double ms;        /* event time of the main kernel and its reduction      */
+} ttn_launch_rec;
+
 /* Opens a profiling window: from now on every contraction kernel launch is
- * bracketed by HIP events on the handle's stream. */
+ * bracketed by HIP events on the handle's stream (one event before the main
+ * kernel, one after its split-K reduction). */
 int ttn_profile_begin(ttn_handle* h);
 
 /* Closes the window (synchronises the stream) and sums the event times and
  * algorithmic flops per kernel class. */
 int ttn_profile_end(ttn_handle* h, ttn_profile* out);
 
+/* The launches of the last window closed by ttn_profile_end, in launch order
+ * (for matching hardware-counter dispatches to launch classes): copies up to
+ * max records into out (may be NULL) and returns how many the window had. */
+int64_t ttn_profile_launches(const ttn_handle* h, ttn_launch_rec* out, int64_t max);
+
 /* The environment rebuild and both sweeps of a step are the same launch
  * sequence every step; by default it is captured once as a HIP graph (on a
  * private stream) and replayed on the handle's stream.  enabled == 0 runs
  * every launch eagerly.  Profiling windows always run eagerly (their timing
- * events need individual launches). */
+ * events need individual launches), and so does every handle of a process
+ * under rocprofv3 hardware-counter collection (ROCPROF_COUNTERS set in the
+ * environment): a counter pass over replayed step graphs ended in a
+ * segmentation fault inside the HIP runtime, eager launches do not. */
 int ttn_set_graphs(ttn_handle* h, int32_t enabled);
 
 /* Checks the launch plan of a configuration without a device: walks

@@ -746,7 +746,8 @@ bool g_dry_run = false;
 
 template <typename R>
 bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen, hipEvent_t ev0,
-           hipEvent_t ev1) {
+           hipEvent_t ev1, CgemmInfo* info) {
+    if (info) *info = CgemmInfo{};
     if (g.M <= 0 || g.N <= 0 || g.B1 * g.B2 <= 0) return true;
     {
         const int64_t km = g.Kin > 0 ? g.Kin - 1 : 0, ko = g.Kout > 0 ? g.Kout - 1 : 0;
@@ -807,6 +808,7 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         }
         const dim3 grid((unsigned)(tiles * splits));
         R* part = (R*)ws.partial;
+        if (info) *info = CgemmInfo{bf16 ? 3 : 2, splits};
         // BF16 path: k-fast operands whose k quads are 16-byte aligned load
         // them as one vector (k tiles start at multiples of 32 in Kin)
         auto quads = [](const void* p, std::initializer_list<int64_t> strides) {
@@ -872,10 +874,12 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         }
 #undef TTN_MFMA_LAUNCH
 #undef TTN_BF16_LAUNCH
-        if (ev1) (void)hipEventRecord(ev1, s);
         if (splits > 1) {
             splitk_reduce(g, splits, (const R*)ws.partial, s);
         }
+        // the timing window closes after the split-K reduction: a launch's
+        // time is the main kernel plus its reduction
+        if (ev1) (void)hipEventRecord(ev1, s);
         return true;
     }
     constexpr int BM = 64, BN = 64, BK = 16;
@@ -898,19 +902,20 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
     const int a_mfast = (g.sam == 1 || g.sak != 1) ? 1 : 0;
     const int b_nfast = (g.sbn == 1 || g.sbk != 1) ? 1 : 0;
     const int64_t blocks = tiles * splits;
+    if (info) *info = CgemmInfo{1, splits};
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL((k_cgemm<R, BM, BN, BK>), dim3((unsigned)blocks), dim3(GEMM_THREADS), 0, s, g,
                        tilesM, tilesN, splits, kchunk, (R*)ws.partial, a_mfast, b_nfast);
-    if (ev1) (void)hipEventRecord(ev1, s);
     if (splits > 1) {
         splitk_reduce(g, splits, (const R*)ws.partial, s);
     }
+    if (ev1) (void)hipEventRecord(ev1, s);
     return true;
 }
 
 template bool cgemm<double>(const Gemm<double>&, const GemmScratch&, hipStream_t, char*, int, hipEvent_t,
-                            hipEvent_t);
+                            hipEvent_t, CgemmInfo*);
 template bool cgemm<float>(const Gemm<float>&, const GemmScratch&, hipStream_t, char*, int, hipEvent_t,
-                           hipEvent_t);
+                           hipEvent_t, CgemmInfo*);
 
 }  // namespace ttn

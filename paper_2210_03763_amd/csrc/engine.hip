@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -124,8 +125,11 @@ struct ttn_handle {
         int prec;        // 0 fp64, 1 fp32
         double flops;    // algorithmic real flops (8 per complex multiply-add)
         bool heff;
+        int kernel = 0;  // CgemmInfo::kernel
+        int splits = 0;
     };
     std::vector<ProfRec> prof_recs;
+    std::vector<ttn_launch_rec> prof_last;   // launches of the last closed window
     int64_t prof_matvecs = 0;
     // reverse mode (checkpoints, tape, adjoints); null until recording starts
     AdjState* adj = nullptr;
@@ -297,8 +301,13 @@ struct Ctx {
         }
         Gemm<R> gg = g;
         if (sizeof(R) == 4 && h->split_bf16) gg.split = 1;
-        if (!cgemm<R>(gg, h->gs, h->stream, why, sizeof(why), e0, e1))
+        CgemmInfo info;
+        if (!cgemm<R>(gg, h->gs, h->stream, why, sizeof(why), e0, e1, &info))
             throw StatusError{TTN_EINVAL, std::string("launch extent check failed: ") + why};
+        if (e0) {
+            h->prof_recs.back().kernel = info.kernel;
+            h->prof_recs.back().splits = info.splits;
+        }
     }
 };
 
@@ -853,6 +862,7 @@ void qr_toward(ttn_handle* h, int DL, int DR, int DP, double* Tv, int leg, doubl
     g.scm = 1;
     g.scn = D;
     c.run(g);
+    rdiag_min(Rout, D, h->st, h->stream);
     (void)n;
 }
 
@@ -1142,6 +1152,11 @@ void accumulate_prof(const std::vector<ttn_handle::ProfRec>& recs, const std::ve
         k.launches += 1;
         k.ms += ms;
         k.flops += r.flops;
+        if (r.kernel == 3) {
+            out->gemm_bf16x3.launches += 1;
+            out->gemm_bf16x3.ms += ms;
+            out->gemm_bf16x3.flops += r.flops;
+        }
         if (r.heff) {
             out->heff.launches += 1;
             out->heff.ms += ms;
@@ -1554,6 +1569,18 @@ int ttn_workspace_query(const ttn_config* cfg, size_t* device_bytes) {
     }
 }
 
+// True when the process runs under rocprofv3 hardware-counter collection
+// (--pmc or a counter input file), which hands its counter list to the
+// profiled process in ROCPROF_COUNTERS.  Step graphs are then not used: a
+// counter pass that captured and replayed the step graph ended in a
+// segmentation fault inside the HIP runtime, while the same graphs replay
+// correctly without counter collection and the same steps launched eagerly
+// run correctly under it.
+bool counter_collection_attached() {
+    const char* c = std::getenv("ROCPROF_COUNTERS");
+    return c && *c;
+}
+
 int ttn_init(const ttn_config* cfg, void* d_workspace, size_t bytes, void* hip_stream, ttn_handle** out) {
     if (!out) return TTN_EINVAL;
     *out = nullptr;
@@ -1563,6 +1590,7 @@ int ttn_init(const ttn_config* cfg, void* d_workspace, size_t bytes, void* hip_s
         if (!d_workspace) return TTN_EINVAL;
         h = new ttn_handle();
         h->stream = (hipStream_t)hip_stream;
+        h->use_graphs = !counter_collection_attached();
         setup_config(h, cfg);
         Bump b(d_workspace, bytes, &h->regions);
         plan(h, b);
@@ -1975,6 +2003,12 @@ int ttn_profile_end(ttn_handle* h, ttn_profile* out) {
         std::memset(out, 0, sizeof(*out));
         accumulate_prof(h->prof_recs, h->ev_pool, out);
         out->matvecs = h->prof_matvecs;
+        h->prof_last.clear();
+        for (const auto& r : h->prof_recs) {
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, h->ev_pool[r.ev], h->ev_pool[r.ev + 1]));
+            h->prof_last.push_back(ttn_launch_rec{r.kernel, r.prec, r.heff ? 1 : 0, r.splits, r.flops, (double)ms});
+        }
         h->prof = false;
         h->prof_recs.clear();
         return TTN_OK;
@@ -1982,6 +2016,14 @@ int ttn_profile_end(ttn_handle* h, ttn_profile* out) {
         h->prof = false;
         return fail(h, e);
     }
+}
+
+int64_t ttn_profile_launches(const ttn_handle* h, ttn_launch_rec* out, int64_t max) {
+    if (!h || max < 0) return TTN_EINVAL;
+    const int64_t n = (int64_t)h->prof_last.size();
+    if (out)
+        for (int64_t i = 0; i < std::min(n, max); ++i) out[i] = h->prof_last[i];
+    return n;
 }
 
 int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t msg_len) {
@@ -2080,7 +2122,7 @@ int ttn_sample(ttn_handle* h, int64_t n_shots, uint64_t seed, int64_t shot0, voi
 
 int ttn_set_graphs(ttn_handle* h, int32_t enabled) {
     if (!h) return TTN_EINVAL;
-    h->use_graphs = enabled != 0;
+    h->use_graphs = enabled != 0 && !counter_collection_attached();
     return TTN_OK;
 }
 

@@ -1243,7 +1243,6 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(const double* G, int 
             mn = v < mn ? v : mn;
         }
         if (s_bad || !(mn == mn)) atomicExch(&st->bad, 1);
-        if (mn > 0) atomicMin(&st->min_rdiag_bits, (unsigned long long)__double_as_longlong(mn));
     }
     // ---------------- inverse by elimination on the identity ----------------
     // Position (i, j), i > j, holds L[i][j] until step j and the partial
@@ -1716,6 +1715,31 @@ void chol_inv(const double* G, int D, double* Linv, double* R, const double* Rpr
     else
         hipLaunchKernelGGL((k_chol_inv<false, 4, 8>), dim3(1), dim3(CHOL_THREADS), 0, s, G, D, Linv, R, Rprev,
                            work, st);
+}
+
+namespace {
+// Smallest real diagonal entry of the D x D (planar, column-major) R of a
+// gauge move, folded into the step's minimum (positive doubles order like
+// their bit patterns).  One wave.
+__global__ __launch_bounds__(64) void k_rdiag_min(const double* R, int D, StepDev* st) {
+    double mn = 1e308;
+    for (int k = threadIdx.x; k < D; k += 64) {
+        const double v = R[k + (int64_t)D * k];
+        mn = v < mn ? v : mn;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(mn, o, 64);
+        mn = t < mn ? t : mn;
+    }
+    if (threadIdx.x == 0 && mn > 0)
+        atomicMin(&st->min_rdiag_bits, (unsigned long long)__double_as_longlong(mn));
+}
+}  // namespace
+
+void rdiag_min(const double* R, int D, StepDev* st, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_rdiag_min, dim3(1), dim3(64), 0, s, R, D, st);
 }
 
 // ---------------------------------------------------------------------------

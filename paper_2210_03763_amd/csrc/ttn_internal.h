@@ -49,12 +49,20 @@ struct GemmScratch {
     int n_regions = 0;
 };
 
+// What a cgemm call launched: the kernel (1 the VALU tile kernel k_cgemm,
+// 2 the MFMA kernel k_cgemm_mfma, 3 the BF16x3 kernel k_cgemm_bf16x3) and
+// the split-K factor (> 1: a k_splitk_reduce* launch follows).
+struct CgemmInfo {
+    int kernel = 0;
+    int splits = 0;
+};
+
 // Validates every operand extent against the region table and launches.
 // Returns false (and launches nothing) when an operand would leave its
 // region; `why` receives a description.
 template <typename R>
 bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen,
-           hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+           hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr, CgemmInfo* info = nullptr);
 
 // When set, launchers validate but enqueue nothing (plan checking without a
 // device).
@@ -146,6 +154,8 @@ void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s, boo
 // dst = sum_{k < count} src_k for planar D x D FP64 matrices stored one after another
 void sum_mats(const double* src, int D, int count, double* dst, hipStream_t s);
 
+// min over k of Re R[k][k] into st->min_rdiag_bits (R: D x D planar)
+void rdiag_min(const double* R, int D, StepDev* st, hipStream_t s);
 // Cholesky of a Hermitian D x D Gram matrix G (planar, column-major):
 // G = L L^H.  Writes Linv (lower, L^{-1}) and R = L^H (upper), or R = L^H * Rprev
 // when Rprev != nullptr (D > 128 only).  Sets st->bad on a non-positive pivot.

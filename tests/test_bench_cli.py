@@ -38,7 +38,7 @@ def test_traffic_summary_tracks_the_contraction_source(tmp_path, monkeypatch):
     import hashlib
     sha = hashlib.sha256(src.read_bytes()).hexdigest()
     summary = tmp_path / "traffic.md"
-    summary.write_text(f"- workload: W1\n- contract_source_sha256: `{sha}`\n- hbm_bytes_per_launch: 123456\n")
+    summary.write_text(f"- workload: W1\n- contract_source_sha256: `{sha}`\n- hbm_bytes_per_heff_launch: 123456\n")
     monkeypatch.setattr(bench, "CONTRACT_SRC", str(src))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(summary))
     assert bench.measured_traffic("W1") == 123456.0
