@@ -1,0 +1,117 @@
+"""The 8x8, d = 4, chi = 128 GHZ-program workload (the bench workload)
+against the oracle and across precisions.
+
+* FP64 path after two steps against the oracle's stored run
+  (tests/golden/c3_oracle_2steps.npz, written by tests/golden/make_golden.py,
+  which calls only oracle/): 256 seeded entries of every node tensor and the
+  whole root tensor within 1e-10 (the gauge is unique: thin QR with real
+  positive R_kk), fidelity, norm^2 and relative energy within 1e-10, the
+  smallest R_kk of each step's gauge moves within 1e-6 relative.
+* FP32 (mixed) and BF16x3 paths: |dF| <= 1e-5 against the oracle's
+  fidelity and C(psi, psi_FP64) <= 1e-5 against the FP64 path (which the
+  first test ties to the oracle entry by entry), Tab. conv8x8's C.
+* Gradient of the GHZ fidelity with respect to the 64 x n_seg pulse table
+  over two recorded steps: mixed and BF16x3 within 1e-5 max|g| of FP64.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2210_03763_amd import ttn as T
+from paper_2210_03763_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle_2steps.npz")
+_FP64 = {}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _fp64_run():
+    if "g" not in _FP64:
+        w = W.config("c3").copy(precision=T.PREC_FP64)
+        _say("[c3] fp64 2 steps")
+        g = T.TTN(w)
+        stats = g.step(2, stats=True)
+        F, _ = g.fidelity()
+        _FP64.update(g=g, stats=stats, F=F)
+    return _FP64
+
+
+def test_c3_fp64_vs_oracle_entries():
+    z = np.load(GOLD)
+    assert str(z["workload"]) == W.config("c3").name and int(z["steps"]) == 2
+    r = _fp64_run()
+    g, stats, F = r["g"], r["stats"], r["F"]
+    flat = g.export_state()
+    shapes = W.node_shapes(64, 4, 128)
+    off = np.concatenate([[0], np.cumsum([a * b * c for a, b, c in shapes])])
+    err = 0.0
+    for v in range(len(shapes)):
+        idx, val = z[f"idx_{v}"], z[f"val_{v}"]
+        err = max(err, float(np.abs(flat[off[v] + idx] - val).max()))
+    root = int(z["root_index"])
+    err_root = float(np.abs(flat[off[root]:off[root + 1]] - z["root"]).max())
+    dN = float(np.abs(np.array([s["norm2"] for s in stats]) - z["norm2"]).max())
+    dE = float(np.abs(np.array([s["energy"] for s in stats]) - z["energy"]).max()) / max(1.0, abs(z["energy"]).max())
+    rrel = float(np.abs(np.array([s["min_r_diag"] for s in stats]) / z["min_r_diag"] - 1).max())
+    res = dict(entry_err=err, root_err=err_root, dF=abs(F - float(z["F"])), dN=dN, dE=dE, min_r_rel=rrel,
+               min_r=[s["min_r_diag"] for s in stats], F=float(z["F"]))
+    _say(f"[c3] fp64 vs oracle {res}")
+    assert err <= 1e-10 and err_root <= 1e-10, res
+    assert res["dF"] <= 1e-10 and dN <= 1e-10 and dE <= 1e-10, res
+    assert rrel <= 1e-6, res
+
+
+@pytest.mark.parametrize("prec", [T.PREC_FP32, T.PREC_BF16X3])
+def test_c3_reduced_precision(prec):
+    z = np.load(GOLD)
+    r = _fp64_run()
+    w = W.config("c3").copy(precision=prec)
+    _say(f"[c3] prec={prec} 2 steps")
+    g = T.TTN(w)
+    stats = g.step(2, stats=True)
+    F, _ = g.fidelity()
+    C = 1 - abs(g.overlap(r["g"])) ** 2
+    res = dict(dF_oracle=abs(F - float(z["F"])), C_fp64=C, dN=abs(stats[-1]["norm2"] - float(z["norm2"][-1])),
+               dE=abs(stats[-1]["energy"] - float(z["energy"][-1])), F=F)
+    _say(f"[c3] {res}")
+    assert res["dF_oracle"] <= 1e-5 and C <= 1e-5, res
+    g.close()
+
+
+def _grad(prec, steps=2):
+    w = W.config("c3").copy(precision=prec)
+    g = T.TTN(w)
+    g.step(1)
+    g.record(steps, 1)
+    g.step(steps)
+    go, gd = g.backward()
+    g.close()
+    return np.concatenate([go.ravel(), gd.ravel()])
+
+
+def test_c3_gradient_mixed_and_bf16x3_vs_fp64():
+    _say("[c3] gradients over 2 recorded steps")
+    g64 = _grad(T.PREC_FP64)
+    scale = float(np.abs(g64).max())
+    out = {}
+    for prec, key in ((T.PREC_FP32, "mixed"), (T.PREC_BF16X3, "bf16x3")):
+        gp = _grad(prec)
+        out[key] = float(np.abs(gp - g64).max())
+    _say(f"[c3] max|g_fp64| {scale:.3e}, max abs differences {out}")
+    assert scale > 0
+    for key, e in out.items():
+        assert e <= 1e-5 * scale, (key, e, scale)
+
+
+def teardown_module(module):
+    if "g" in _FP64:
+        _FP64["g"].close()
+        _FP64.clear()

@@ -54,9 +54,11 @@ def compare(w, n_steps=None, tol=1e-10, tolC=None, check_energy=True):
     ov = O.ttn_overlap(st, gs)
     Cst = 1 - abs(ov) ** 2
     n2g, Eg = stats[-1]["norm2"], stats[-1]["energy"]
+    # smallest R_kk of the step's gauge moves (the QR conditioning monitor)
+    rrel = max(abs(s["min_r_diag"] - r["min_r_diag"]) / r["min_r_diag"] for s, r in zip(stats, recs))
     res = dict(dF=abs(Fg - Fo), C=Cst, dN=abs(n2g - recs[-1]["norm2"]),
                dE=abs(Eg - recs[-1]["energy"]) / max(1.0, abs(recs[-1]["energy"])), F=Fo,
-               min_r=min(s["min_r_diag"] for s in stats))
+               min_r=min(s["min_r_diag"] for s in stats), min_r_rel=rrel)
     _say(f"[parity] {res}")
     tolC = tol if tolC is None else tolC
     assert res["dF"] <= tol, res
@@ -64,6 +66,8 @@ def compare(w, n_steps=None, tol=1e-10, tolC=None, check_energy=True):
     assert res["dN"] <= tol, res
     if check_energy:
         assert res["dE"] <= tol, res
+    if w.precision == T.PREC_FP64:
+        assert rrel <= 1e-6, res
     g.close()
     return res
 
@@ -142,3 +146,57 @@ def test_undressed_rank_deficient_state_reports_enumeric():
         g = T.TTN(w)
         g.step(1)
     assert e.value.code == T.TTN_ENUMERIC
+
+
+def test_interaction_cutoff_fp64():
+    # interaction-range cut-off (Sec. "Tensor network simulations"): pairs
+    # farther than r_cut = 1.2 dropped (only nearest neighbours kept), 4x4
+    # chi=16 dressed drive, 20 steps
+    w = W.config("c1-ent").copy(r_cut=1.2)
+    compare(w)
+    # the cut is effective: the all-pairs oracle run ends in another state
+    # (C = 1.2e-7 between the two)
+    st_cut, _ = O.run(w, record=False)
+    st_all, _ = O.run(w.copy(r_cut=0.0), record=False)
+    C = 1 - abs(O.ttn_overlap(st_cut, st_all)) ** 2
+    assert C > 1e-8, C
+
+
+def test_nonfinite_pulses_rejected_state_unchanged():
+    # a NaN in the pulse table is rejected before any device work
+    # (TTN_EINVAL), and the handle keeps its program and state
+    w = W.config("c1-ent").copy(n_steps=2)
+    g = T.TTN(w)
+    g.step(1)
+    before = g.export_state()
+    om = np.array(w.omega, copy=True)
+    om[3, 1] = np.nan
+    with pytest.raises(T.TTNError) as e:
+        g.set_pulses(w.seg_edges, om, w.delta, w.events)
+    assert e.value.code == T.TTN_EINVAL
+    assert np.array_equal(g.export_state(), before)
+    g.step(1)
+    st, _ = O.run(w, n_steps=2)
+    Fo, _ = st.ghz_fidelity(w.target_sites)
+    assert abs(g.fidelity()[0] - Fo) < 1e-10
+    g.close()
+
+
+def test_zero_hamiltonian_is_a_happy_breakdown():
+    # every drive zero and C6 = 0: H = 0, so every Krylov recursion breaks
+    # down after its first vector (beta_1 = 0) and each step is the identity;
+    # the state changes only by the rounding of the gauge moves (2x2 at
+    # maximal chi, dressed so that every gauge move is full rank)
+    w = W.make_random_drive(2, 2, 3, 9, 4, 0.05, 2, seed=3, plus_sites=(0, 1, 2, 3), eps=0.1)
+    w.omega[:] = 0.0
+    w.delta[:] = 0.0
+    w.c6 = 0.0
+    g = T.TTN(w)
+    before = g.export_state()
+    F0, _ = g.fidelity()
+    stats = g.step(4, stats=True)
+    after = g.export_state()
+    assert all(s["min_krylov"] == 1 for s in stats), stats
+    assert np.abs(after - before).max() < 1e-12
+    assert abs(g.fidelity()[0] - F0) < 1e-13
+    g.close()
