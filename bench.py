@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 
 METRIC = "TDVP steps/sec + H_eff MFMA util, 8x8 chi=128; mixed vs FP64 at 1e-5 fidel"
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+HBM_PEAK_GBS = 8000.0
 CONTRACT_SRC = os.path.join(ROOT, "paper_2210_03763_amd", "csrc", "contract.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heff_contract_f32_8x8_d4_chi128_mixed_hbm_traffic.md")
 
@@ -167,7 +168,7 @@ def calibration_copy(mib):
           flush=True)
 
 
-def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True, launch_log=None):
+def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True, launch_log=None, timed_window=True):
     """Warm-up steps (the first captures the step graph), `steps` timed steps
     replayed from the graph, then -- with profile -- `steps` more steps in a
     profiling window (launched eagerly, each contraction bracketed by HIP
@@ -192,7 +193,7 @@ def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True, launch_log
     if profile:
         if calib_mib > 0:
             calibration_copy(calib_mib)
-        g.profile_begin()
+        g.profile_begin(timed=timed_window)
         t2 = time.perf_counter()
         g.step(steps)
         torch.cuda.synchronize()
@@ -201,17 +202,29 @@ def run_gpu(w, steps, warmup, profile=True, calib_mib=0, graphs=True, launch_log
         ms_prof = (t3 - t2) * 1e3 / steps
         if launch_log:
             with open(launch_log, "w") as f:
-                json.dump({"workload": w.name, "steps": steps, "launches": g.profile_launches()}, f)
+                json.dump({"workload": w.name, "steps": steps, "timed": timed_window,
+                           "heff_event_ms": prof.heff.ms, "heff_flops": prof.heff.flops,
+                           "launches": g.profile_launches()}, f)
         print(f"[bench] {steps} profiled step(s) done", file=sys.stderr, flush=True)
     F, _ = g.fidelity()
     n2, E = g.observables()
     return g, (t1 - t0) * 1e3 / steps, prof, ms_prof, F, n2, E
 
 
-def run_adjoint(w, steps, ckpt=10):
+def adjoint_target(w):
+    """Target sites of the forward+adjoint measurement: the atoms the program
+    has rotated at its first step.  Early in the program the all-atom GHZ
+    fidelity depends only on the |0...0> amplitude, which no drive touches,
+    so its gradient vanishes up to rounding; the GHZ state of the rotated
+    atoms has a gradient of order 1e-5 there."""
+    return sorted({s for (k, s, _) in w.events if k == 0}) or list(range(w.n_sites))
+
+
+def run_adjoint(w, steps, ckpt=10, target=None):
     """Forward + adjoint: `steps` recorded steps (a state checkpoint every
     `ckpt` steps) and the backward pass of the GHZ fidelity gradient, timed
-    separately."""
+    separately.  Returns the timings and the gradient (omega, delta)."""
+    import numpy as np
     import torch
     from paper_2210_03763_amd import ttn
     g = ttn.TTN(w, device="cuda:0")
@@ -222,7 +235,7 @@ def run_adjoint(w, steps, ckpt=10):
     g.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    go, gd = g.backward()
+    go, gd = g.backward(target_sites=target)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     g.close()
@@ -231,7 +244,7 @@ def run_adjoint(w, steps, ckpt=10):
     fwd, bwd = (t1 - t0) / steps, (t2 - t1) / steps
     return {"steps": steps, "ckpt_every": ckpt, "fwd_ms_per_step": round(1e3 * fwd, 2), "bwd_ms_per_step": round(1e3 * bwd, 2),
             "fwd_adj_steps_per_s": round(1.0 / (fwd + bwd), 4), "adjoint_buffer_gib": round(nbytes / 2 ** 30, 2),
-            "max_abs_grad": float(max(abs(go).max(), abs(gd).max()))}
+            "max_abs_grad": float(max(abs(go).max(), abs(gd).max()))}, np.concatenate([go.ravel(), gd.ravel()])
 
 
 def run_contract_stage(stage, reps=5, chi=128, precision=1):
@@ -415,6 +428,274 @@ def run_sampling(w, shots, warm_steps=2):
             "probability_covered": float((abs(amp[first]) ** 2).sum())}
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (python bench.py --summarize-profile DIR)
+# ---------------------------------------------------------------------------
+# DIR holds up to three rocprofv3 output folders of bench.py runs with
+# --calib-copy-mib and --launch-log: trace/ (--kernel-trace --stats), fetch/
+# (--pmc FETCH_SIZE) and write/ (--pmc WRITE_SIZE), each with its
+# launches.json.  A run's profiling window starts right after the calibration
+# kernel (the dispatch whose name contains "neg_kernel"); in it, contraction
+# launches are the dispatches named k_cgemm_mfma<...>, k_cgemm_bf16x3<...> or
+# k_cgemm<...> (the main kernels), each followed by its k_splitk_reduce* dispatch
+# when the launch record says split-K > 1.  The i-th main dispatch after the
+# calibration kernel is the i-th record of launches.json; its kernel class and
+# operand precision are checked against the kernel name.
+
+CONTRACT_MAIN = ("k_cgemm_mfma<", "k_cgemm_bf16x3<", "k_cgemm<")
+KERNEL_CLASS = {"k_cgemm<": 1, "k_cgemm_mfma<": 2, "k_cgemm_bf16x3<": 3}
+
+
+def _short(name: str) -> str:
+    """Kernel name without namespace, return type and argument list."""
+    n = name
+    for pre in ("void ", "ttn::(anonymous namespace)::", "(anonymous namespace)::"):
+        n = n.replace(pre, "")
+    depth, cut = 0, None
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    return n[:cut] if cut else n
+
+
+def _main_class(short: str):
+    for pre in CONTRACT_MAIN:
+        if short.startswith(pre):
+            return KERNEL_CLASS[pre], ("double" if short[len(pre):].startswith("double") else "float")
+    return None, None
+
+
+def _read_rows(folder: str, suffix: str):
+    import csv
+    import glob
+    import gzip
+    hits = sorted(glob.glob(os.path.join(folder, "**", f"*{suffix}"), recursive=True) +
+                  glob.glob(os.path.join(folder, "**", f"*{suffix}.gz"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {folder}")
+    path = hits[0]
+    f = gzip.open(path, "rt") if path.endswith(".gz") else open(path)
+    with f:
+        return list(csv.DictReader(f)), path
+
+
+def match_window(dispatches, launches):
+    """dispatches: [(dispatch_id, kernel_name, payload)] in dispatch order.
+    Returns (first, last, pairs): the window's dispatch index range and, per
+    launch record, (record, main index, reduction index or None)."""
+    cal = [i for i, d in enumerate(dispatches) if "neg_kernel" in d[1]]
+    if not cal:
+        raise ValueError("calibration kernel not found")
+    i = cal[-1] + 1
+    pairs = []
+    for rec in launches:
+        while i < len(dispatches) and _main_class(_short(dispatches[i][1]))[0] is None:
+            i += 1
+        if i >= len(dispatches):
+            raise ValueError(f"ran out of dispatches at launch {len(pairs)}")
+        cls, prec = _main_class(_short(dispatches[i][1]))
+        want_prec = "float" if rec["prec"] == 1 else "double"
+        if cls != rec["kernel"] or prec != want_prec:
+            raise ValueError(f"launch {len(pairs)}: dispatch {_short(dispatches[i][1])} does not match "
+                             f"record class {rec['kernel']} / {want_prec}")
+        main = i
+        i += 1
+        red = None
+        if rec["splits"] > 1:
+            while i < len(dispatches) and "k_splitk_reduce" not in dispatches[i][1]:
+                if _main_class(_short(dispatches[i][1]))[0] is not None:
+                    raise ValueError(f"launch {len(pairs)}: split-K reduction missing")
+                i += 1
+            red = i
+            i += 1
+        pairs.append((rec, main, red))
+    return cal[-1] + 1, i - 1, pairs
+
+
+def _trace_summary(folder, launches_json):
+    rows, path = _read_rows(folder, "kernel_trace.csv")
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    disp = [(int(r["Dispatch_Id"]), r["Kernel_Name"],
+             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6) for r in rows]
+    L = json.load(open(launches_json))
+    first, last, pairs = match_window(disp, L["launches"])
+    dur = lambda k: disp[k][2] if k is not None else 0.0  # noqa: E731
+
+    def cls(sel):
+        ps = [p for p in pairs if sel(p[0])]
+        ms = sum(dur(m) + dur(r) for _, m, r in ps)
+        fl = sum(p[0]["flops"] for p in ps)
+        ev = sum(p[0]["ms"] for p in ps)
+        return {"launches": len(ps), "ms": ms, "avg_ms": ms / max(1, len(ps)), "flops": fl,
+                "tflops": fl / 1e12 / (ms / 1e3) if ms > 0 else 0.0, "event_ms": ev,
+                "reductions": sum(1 for _, _, r in ps if r is not None)}
+    # the launches of each H_eff / K_eff matvec, spanned from its first main
+    # kernel's start to its last kernel's end
+    mv = {}
+    for rec, m, r in pairs:
+        if rec["heff"] == 1 and rec["prec"] == 1:
+            a, b = mv.get(rec["matvec"], (None, None))
+            last = r if r is not None else m
+            mv[rec["matvec"]] = (m if a is None else a, last)
+    span_heff = sum((int(rows[b]["End_Timestamp"]) - int(rows[a]["Start_Timestamp"])) * 1e-6 for a, b in mv.values())
+    fam = {}
+    for k in range(first, last + 1):
+        n = _short(disp[k][1])
+        c, t = fam.get(n, (0, 0.0))
+        fam[n] = (c + 1, t + disp[k][2])
+    span = (int(rows[last]["End_Timestamp"]) - int(rows[first]["Start_Timestamp"])) * 1e-6
+    return dict(path=path, workload=L["workload"], steps=L["steps"], first=first, last=last, n_matvecs=len(mv),
+                heff_span_ms=span_heff, heff_event_ms=L.get("heff_event_ms"),
+                heff=cls(lambda r: r["heff"] == 1 and r["prec"] == 1),
+                f32=cls(lambda r: r["prec"] == 1), f64=cls(lambda r: r["prec"] == 0),
+                families=fam, kernel_ms=sum(v[1] for v in fam.values()), span_ms=span)
+
+
+def _counter_summary(folder, launches_json, counter):
+    rows, path = _read_rows(folder, "counter_collection.csv")
+    by = {}
+    for r in rows:
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        nm, v = by.get(d, (r["Kernel_Name"], 0.0))
+        by[d] = (nm, v + float(r["Counter_Value"]))
+    disp = [(d, by[d][0], by[d][1]) for d in sorted(by)]
+    L = json.load(open(launches_json))
+    first, last, pairs = match_window(disp, L["launches"])
+    cal = disp[first - 1][2]
+    val = lambda k: disp[k][2] if k is not None else 0.0  # noqa: E731
+    heff = [p for p in pairs if p[0]["heff"] == 1 and p[0]["prec"] == 1]
+    allf = [p for p in pairs if p[0]["prec"] == 1]
+    return dict(path=path, calib_kib=cal, launches=len(pairs),
+                heff_kib=sum(val(m) + val(r) for _, m, r in heff), n_heff=len(heff),
+                f32_kib=sum(val(m) + val(r) for _, m, r in allf), n_f32=len(allf))
+
+
+def summarize_profile(profdir, calib_mib=256, out_dir=None):
+    """Writes the kernel-trace and HBM-traffic summaries under profiles/."""
+    import hashlib
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    written = []
+    base = ("--steps 1 --warmup 1 --no-fp64 --no-cpu --adjoint-steps 0 --sample-shots 0 --open-gamma 0 "
+            "--bf16-steps 0 --calib-copy-mib 256")
+    tdir = os.path.join(profdir, "trace")
+    if os.path.isdir(tdir):
+        t = _trace_summary(tdir, os.path.join(tdir, "launches.json"))
+        h, f = t["heff"], t["f32"]
+        lines = [
+            "# Kernel trace: one mixed-precision TDVP step, 8x8, d=4, chi=128",
+            "",
+            f"Workload: {t['workload']} (the bench workload: GHZ-preparation program, Krylov dimension 12).",
+            "Window: the dispatches of the profiled step (launched eagerly inside the library's profiling",
+            "window), from the one after the calibration kernel (name containing `neg_kernel`) to the",
+            "window's last contraction launch.",
+            "",
+            "Command (R = repository root on the GPU box), then the summary:",
+            "",
+            "```",
+            f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+            f"-d $R/gpurun_out/prof/trace -o run -- python3 $R/bench.py {base} "
+            f"--launch-log $R/gpurun_out/prof/trace/launches.json",
+            "python bench.py --summarize-profile gpurun_out/prof",
+            "```",
+            "",
+            "Kernel-name filter of the contraction launches: main kernels `k_cgemm_mfma<...>`,",
+            "`k_cgemm_bf16x3<...>`, `k_cgemm<...>`; each followed by its `k_splitk_reduce<...>` or",
+            "`k_splitk_reduce_vec<...>` dispatch when the launch record has split-K > 1 (both counted).",
+            "The i-th main dispatch is the i-th record of the library's launch log (kernel class and",
+            "operand precision checked); H_eff/K_eff launches are the records flagged heff.",
+            "",
+            f"Kernel time in the window: {t['kernel_ms']:.1f} ms over {t['last'] - t['first'] + 1} dispatches; "
+            f"first-to-last dispatch span {t['span_ms']:.1f} ms.",
+            "",
+            "| launch class | launches | with reduction | device ms (main + reduction) | avg ms per launch | "
+            "algorithmic TFLOP/s |",
+            "|---|---|---|---|---|---|",
+        ]
+        for key, lab in (("heff", "H_eff/K_eff matvecs, FP32 (roofline kernel)"), ("f32", "all FP32 contractions"),
+                         ("f64", "all FP64 contractions (gauge moves)")):
+            c = t[key]
+            lines.append(f"| {lab} | {c['launches']} | {c['reductions']} | {c['ms']:.2f} | {c['avg_ms']:.5f} | "
+                         f"{c['tflops']:.1f} |")
+        ev = t["heff_event_ms"] or 0.0
+        lines += ["",
+                  "H_eff/K_eff launches, three measures of the same work (the library times each matvec's",
+                  "launches between one event pair; `roofline.avg_launch_ms` of bench.py is that event time per",
+                  "launch):", "",
+                  f"- heff_launches: {h['launches']}",
+                  f"- heff_kernel_ms (sum of kernel durations, main + reduction): {h['ms']:.2f}",
+                  f"- heff_span_ms (first kernel start to last kernel end of each matvec, {t['n_matvecs']} matvecs): "
+                  f"{t['heff_span_ms']:.2f}",
+                  f"- heff_event_ms (library events, this run): {ev:.2f}",
+                  f"- heff_avg_launch_ms: {h['avg_ms']:.5f} (kernels), {t['heff_span_ms'] / h['launches']:.5f} "
+                  f"(spans), {ev / h['launches']:.5f} (events)",
+                  f"- heff_tflops_algorithmic: {h['tflops']:.2f} (kernels), "
+                  f"{h['flops'] / 1e12 / (t['heff_span_ms'] / 1e3):.2f} (spans)",
+                  f"- heff_frac_of_fp32_peak: {h['tflops'] / PEAK_TFLOPS['fp32']:.4f} (kernels), "
+                  f"{h['flops'] / 1e12 / (t['heff_span_ms'] / 1e3) / PEAK_TFLOPS['fp32']:.4f} (spans)", "",
+                  "| kernel | calls | total ms | avg us | % of window |", "|---|---|---|---|---|"]
+        for n, (c, ms) in sorted(t["families"].items(), key=lambda kv: -kv[1][1])[:40]:
+            lines.append(f"| `{n}` | {c} | {ms:.2f} | {1e3 * ms / c:.1f} | {100 * ms / t['kernel_ms']:.1f} |")
+        p = os.path.join(out_dir, "tdvp_step_8x8_d4_chi128_mixed_kernel_trace.md")
+        open(p, "w").write("\n".join(lines) + "\n")
+        written.append(p)
+    fdir, wdir = os.path.join(profdir, "fetch"), os.path.join(profdir, "write")
+    if os.path.isdir(fdir) and os.path.isdir(wdir):
+        fs = _counter_summary(fdir, os.path.join(fdir, "launches.json"), "FETCH_SIZE")
+        ws = _counter_summary(wdir, os.path.join(wdir, "launches.json"), "WRITE_SIZE")
+        known = calib_mib * 1024.0
+        ff, wf = known / fs["calib_kib"], known / ws["calib_kib"]
+        fb = fs["heff_kib"] * 1024 * ff / fs["n_heff"]
+        wb = ws["heff_kib"] * 1024 * wf / ws["n_heff"]
+        fba = fs["f32_kib"] * 1024 * ff / fs["n_f32"]
+        wba = ws["f32_kib"] * 1024 * wf / ws["n_f32"]
+        sha = hashlib.sha256(open(CONTRACT_SRC, "rb").read()).hexdigest()
+        L = json.load(open(os.path.join(fdir, "launches.json")))
+        cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 420 rocprofv3 --pmc {c} --kernel-include-regex "
+               "\"k_cgemm|k_splitk_reduce|neg_kernel\" --output-format csv -d $R/gpurun_out/prof/{d} -o run -- "
+               "python3 $R/bench.py {b} --no-graphs --untimed-window --launch-log $R/gpurun_out/prof/{d}/launches.json")
+        lines = [
+            "# HBM traffic of the H_eff/K_eff contraction launches, 8x8, d=4, chi=128 (mixed)",
+            "",
+            "Two counter passes, one counter each (R = repository root on the GPU box), then the summary:",
+            "",
+            "```",
+            cmd.format(c="FETCH_SIZE", d="fetch", b=base),
+            cmd.format(c="WRITE_SIZE", d="write", b=base),
+            "python bench.py --summarize-profile gpurun_out/prof",
+            "```",
+            "",
+            "Kernel-name filter: the counter passes record only dispatches matching",
+            "`k_cgemm|k_splitk_reduce|neg_kernel`.  Window and launch matching as in the kernel-trace",
+            "summary: the i-th main contraction dispatch after the calibration kernel is the i-th record of",
+            "the launch log; a launch's bytes are its main kernel's plus its split-K reduction's.  Counter",
+            "values (KiB per dispatch) are scaled by known bytes / counter reading of the calibration kernel",
+            f"(a streaming kernel that reads and writes {calib_mib} MiB once).",
+            "",
+            f"- workload: {L['workload']}",
+            f"- contract_source_sha256: `{sha}`",
+            f"- calibration FETCH_SIZE reading: {fs['calib_kib']:.1f} KiB for {known:.0f} KiB read (factor {ff:.4f})",
+            f"- calibration WRITE_SIZE reading: {ws['calib_kib']:.1f} KiB for {known:.0f} KiB written "
+            f"(factor {wf:.4f})",
+            f"- heff_launches: {fs['n_heff']}",
+            f"- fetch_bytes_per_heff_launch: {fb:.0f}",
+            f"- write_bytes_per_heff_launch: {wb:.0f}",
+            f"- hbm_bytes_per_heff_launch: {fb + wb:.0f}",
+            f"- fp32_contraction_launches: {fs['n_f32']}",
+            f"- hbm_bytes_per_fp32_launch: {fba + wba:.0f}",
+        ]
+        p = os.path.join(out_dir, "heff_contract_f32_8x8_d4_chi128_mixed_hbm_traffic.md")
+        open(p, "w").write("\n".join(lines) + "\n")
+        written.append(p)
+    return written
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +717,8 @@ def main():
                     help="launch every step eagerly (for counter collection; kernels are the same)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--untimed-window", action="store_true",
+                    help="profiling window without HIP events (for hardware-counter passes)")
     ap.add_argument("--launch-log", default=None,
                     help="write the profiling window's contraction launch records (JSON) here")
     ap.add_argument("--bf16-steps", type=int, default=2,
@@ -446,7 +729,13 @@ def main():
                     help="time one H_eff contraction stage of a 128^3 node instead (kernel profiling)")
     ap.add_argument("--contract-precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="arithmetic of --contract-stage")
+    ap.add_argument("--summarize-profile", default=None, metavar="DIR",
+                    help="write the profiles/ summaries from rocprofv3 output under DIR (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_profile:
+        for p in summarize_profile(args.summarize_profile, args.calib_copy_mib or 256):
+            print(p, flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the TDVP sweep is sequential "
               f"over tree nodes and the library has no multi-GPU path", file=sys.stderr, flush=True)
@@ -467,7 +756,8 @@ def main():
     gm, ms_mixed, prof, ms_prof, F_m, n2_m, E_m = run_gpu(w, args.steps, args.warmup,
                                                           calib_mib=args.calib_copy_mib,
                                                           graphs=not args.no_graphs,
-                                                          launch_log=args.launch_log)
+                                                          launch_log=args.launch_log,
+                                                          timed_window=not args.untimed_window)
     print(f"[bench] mixed {ms_mixed:.1f} ms/step F={F_m:.12f}", file=sys.stderr, flush=True)
     dt = "fp32" if w.precision == ttn.PREC_FP32 else "fp64"
     kall = prof.gemm_f32 if w.precision == ttn.PREC_FP32 else prof.gemm_f64
@@ -479,7 +769,8 @@ def main():
             "frac": round(achieved / PEAK_TFLOPS[dt], 4),
             "traffic": measured_traffic(w.name) if dt == "fp32" else None,
             "kernel": f"H_eff/K_eff matvec launches of the complex {dt.upper()} contraction kernel "
-                      f"(k_cgemm_mfma / k_cgemm, each timed with its split-K reduction)",
+                      f"(k_cgemm_mfma / k_cgemm with their split-K reductions); each matvec's launches run "
+                      f"back to back between one pair of HIP events",
             "launches": int(k.launches), "avg_launch_ms": round(avg_ms, 5),
             "algorithmic_gflop_per_launch": round(k.flops / max(1, k.launches) / 1e9, 4),
             "matvecs": int(prof.matvecs),
@@ -489,6 +780,16 @@ def main():
                                  "heff_share_of_flops": round(k.flops / max(1.0, kall.flops), 4)},
             "window": f"the {args.steps} steps after the timed ones, launched eagerly inside a profiling "
                       f"window ({ms_prof:.1f} ms/step there); kernel durations do not depend on graph replay"}
+    def vec(p):
+        gbs = p.bytes / 1e9 / (p.ms / 1e3) if p.ms > 0 else 0.0
+        return {"calls": int(p.calls), "ms_per_step": round(p.ms / args.steps, 3),
+                "gbytes_per_step": round(p.bytes / 1e9 / args.steps, 3), "achieved_gb_per_s": round(gbs, 1),
+                "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    hbm = {"peak_gb_per_s": HBM_PEAK_GBS,
+           "lanczos_vectors_all": vec(prof.lanczos),
+           "lanczos_vectors_ge_2^20": vec(prof.lanczos_large),
+           "bytes": "what the Lanczos vector kernels read and write by construction (16 B per complex FP64 "
+                    "element, 8 B per FP32 one), HIP events around each call in the profiling window"}
     out = {"metric": METRIC, "value": round(1e3 / ms_mixed, 4), "unit": "steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_mixed, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
@@ -498,7 +799,7 @@ def main():
                       "precision": "complex FP32 contractions, FP64 Lanczos/QR/environments"
                       if dt == "fp32" else "FP64",
                       "heff_tflop_per_step": round(fps / 1e12, 3)},
-           "roofline": roof}
+           "roofline": roof, "hbm_bound_kernels": hbm}
     if not args.no_fp64 and w.precision == ttn.PREC_FP32:
         w64 = w.copy(precision=ttn.PREC_FP64)
         print(f"[bench] fp64 run: {args.steps} steps", file=sys.stderr, flush=True)
@@ -515,13 +816,29 @@ def main():
         g64.close()
     gm.close()
     if args.adjoint_steps > 0:
+        import numpy as np
         print(f"[bench] forward+adjoint: {args.adjoint_steps} recorded steps", file=sys.stderr, flush=True)
-        adj = {"mixed": run_adjoint(w, args.adjoint_steps, args.adjoint_ckpt)}
+        tgt = adjoint_target(w)
+        adj = {"target_sites": tgt}
+        grads = {}
+        legs = [("mixed", w.precision)]
         if not args.no_fp64 and w.precision == ttn.PREC_FP32:
-            adj["fp64"] = run_adjoint(w.copy(precision=ttn.PREC_FP64), args.adjoint_steps, args.adjoint_ckpt)
-            adj["mixed_speedup_fwd_adj"] = round(adj["fp64"]["fwd_ms_per_step"] + adj["fp64"]["bwd_ms_per_step"], 2) / \
-                max(1e-9, adj["mixed"]["fwd_ms_per_step"] + adj["mixed"]["bwd_ms_per_step"])
-            adj["mixed_speedup_fwd_adj"] = round(adj["mixed_speedup_fwd_adj"], 3)
+            legs += [("fp64", ttn.PREC_FP64)]
+            if args.bf16_steps > 0:
+                legs += [("bf16x3", ttn.PREC_BF16X3)]
+        for key, prec in legs:
+            adj[key], grads[key] = run_adjoint(w.copy(precision=prec), args.adjoint_steps, args.adjoint_ckpt, tgt)
+        if "fp64" in grads:
+            tot = lambda k: adj[k]["fwd_ms_per_step"] + adj[k]["bwd_ms_per_step"]  # noqa: E731
+            scale = float(np.abs(grads["fp64"]).max())
+            adj["max_abs_grad_fp64"] = scale
+            for key in grads:
+                if key == "fp64":
+                    continue
+                e = float(np.abs(grads[key] - grads["fp64"]).max())
+                adj[f"{key}_speedup_fwd_adj"] = round(tot("fp64") / max(1e-9, tot(key)), 3)
+                adj[f"{key}_max_abs_grad_diff"] = e
+                adj[f"{key}_max_rel_grad_diff"] = e / scale if scale > 0 else None
         out["forward_adjoint"] = adj
     if args.open_gamma > 0:
         print(f"[bench] open system: gamma {args.open_gamma}, {args.steps} steps", file=sys.stderr, flush=True)

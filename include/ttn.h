@@ -255,12 +255,29 @@ typedef struct {
                                of the contraction (M N K per launch)            */
 } ttn_kernel_prof;
 
+/* Device time of the Lanczos vector kernels (projections, Gram-Schmidt
+ * subtractions, norms, scaling, recombination) of the general Krylov path. */
+typedef struct {
+    int64_t calls;          /* wrapper calls (each one to three kernel launches) */
+    double ms;              /* summed device time between events around them     */
+    double bytes;           /* bytes those kernels read and write by construction
+                               (16 per complex FP64 element, 8 per FP32 one)     */
+} ttn_vec_prof;
+
+/* Launch counts and flops per class cover every contraction launch of the
+ * window.  Times: the launches of one H_eff / K_eff matvec run back to back
+ * between one pair of HIP events (heff.ms sums those matvec times, and they
+ * count in the ms of their precision class); every other contraction launch
+ * is bracketed by its own pair (before the main kernel, after its split-K
+ * reduction).  gemm_bf16x3.ms holds only such individually timed launches. */
 typedef struct {
     ttn_kernel_prof gemm_f32;   /* complex FP32 contraction kernel (incl. BF16x3) */
     ttn_kernel_prof gemm_f64;   /* complex FP64 contraction kernel               */
     ttn_kernel_prof heff;       /* the subset that applies H_eff / K_eff         */
     int64_t matvecs;            /* H_eff / K_eff applications                     */
     ttn_kernel_prof gemm_bf16x3; /* the FP32 launches that ran the BF16x3 kernel  */
+    ttn_vec_prof lanczos;       /* Lanczos vector kernels, every operator size    */
+    ttn_vec_prof lanczos_large; /* the subset on vectors of >= 2^20 elements      */
 } ttn_profile;
 
 /* One contraction launch of a profiling window, in launch order. */
@@ -270,15 +287,25 @@ typedef struct {
     int32_t prec;     /* 0 FP64 operands, 1 FP32 operands                     */
     int32_t heff;     /* 1 when the launch applies H_eff / K_eff              */
     int32_t splits;   /* split-K factor; > 1: a k_splitk_reduce* launch follows
-                         the main kernel and is timed with it                 */
+                         the main kernel                                      */
+    int32_t matvec;   /* ordinal of the H_eff / K_eff matvec in the window the
+                         launch belongs to, -1 for other launches             */
+    int32_t reserved;
     double flops;     /* algorithmic real flops (8 M N K)                     */
-    double ms;        /* event time of the main kernel and its reduction      */
+    double ms;        /* event time of the main kernel and its reduction; -1
+                         for H_eff / K_eff launches (timed per matvec) and in
+                         untimed windows                                      */
 } ttn_launch_rec;
 
-/* Opens a profiling window: from now on every contraction kernel launch is
- * bracketed by HIP events on the handle's stream (one event before the main
- * kernel, one after its split-K reduction). */
+/* Opens a profiling window: from now on contraction launches are recorded
+ * and timed with HIP events on the handle's stream (see ttn_profile), and so
+ * are the Lanczos vector kernels of the general Krylov path. */
 int ttn_profile_begin(ttn_handle* h);
+
+/* The same window without any event: launches are only recorded (class,
+ * split factor, H_eff flag, flops) and ttn_profile's times stay 0.  For runs
+ * under hardware-counter collection, which should see plain dispatches. */
+int ttn_profile_begin_untimed(ttn_handle* h);
 
 /* Closes the window (synchronises the stream) and sums the event times and
  * algorithmic flops per kernel class. */
@@ -293,10 +320,7 @@ int64_t ttn_profile_launches(const ttn_handle* h, ttn_launch_rec* out, int64_t m
  * sequence every step; by default it is captured once as a HIP graph (on a
  * private stream) and replayed on the handle's stream.  enabled == 0 runs
  * every launch eagerly.  Profiling windows always run eagerly (their timing
- * events need individual launches), and so does every handle of a process
- * under rocprofv3 hardware-counter collection (ROCPROF_COUNTERS set in the
- * environment): a counter pass over replayed step graphs ended in a
- * segmentation fault inside the HIP runtime, eager launches do not. */
+ * events need individual launches). */
 int ttn_set_graphs(ttn_handle* h, int32_t enabled);
 
 /* Checks the launch plan of a configuration without a device: walks

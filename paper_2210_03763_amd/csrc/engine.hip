@@ -7,7 +7,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -119,17 +118,31 @@ struct ttn_handle {
     // profiling window: event pairs around GEMM kernel launches
     bool prof = false;
     bool in_heff = false;
+    bool prof_timed = true;   // false: launches are recorded, no events
     std::vector<hipEvent_t> ev_pool;
+    int ev_used = 0;
+    struct MatvecRec {
+        int ev;          // event pair around every contraction launch of one matvec
+        double flops;
+    };
+    std::vector<MatvecRec> mv_recs;
     struct ProfRec {
-        int ev;          // index of the begin event; end event is ev + 1
+        int ev;          // begin event (end: ev + 1), -1 when timed per matvec
         int prec;        // 0 fp64, 1 fp32
         double flops;    // algorithmic real flops (8 per complex multiply-add)
         bool heff;
         int kernel = 0;  // CgemmInfo::kernel
         int splits = 0;
+        int matvec = -1;
     };
     std::vector<ProfRec> prof_recs;
     std::vector<ttn_launch_rec> prof_last;   // launches of the last closed window
+    struct VecRec {
+        int ev;
+        double bytes;    // bytes the Lanczos vector kernels of the call read and write
+        int64_t n;       // complex elements per vector
+    };
+    std::vector<VecRec> vec_recs;
     int64_t prof_matvecs = 0;
     // reverse mode (checkpoints, tape, adjoints); null until recording starts
     AdjState* adj = nullptr;
@@ -280,6 +293,19 @@ void plan(ttn_handle* h, Bump& b) {
 // ---------------------------------------------------------------------------
 // GEMM helpers on node tensors T[l, r, p] (l fastest), planar complex
 // ---------------------------------------------------------------------------
+// k consecutive events of the profiling pool (created on first use); returns
+// the index of the first.  The pool restarts at every profiling window.
+int take_events(ttn_handle* h, int k) {
+    const int idx = h->ev_used;
+    h->ev_used += k;
+    while ((int)h->ev_pool.size() < h->ev_used) {
+        hipEvent_t e;
+        HIPCHECK(hipEventCreate(&e));
+        h->ev_pool.push_back(e);
+    }
+    return idx;
+}
+
 template <typename R>
 struct Ctx {
     ttn_handle* h;
@@ -287,27 +313,45 @@ struct Ctx {
     void run(const Gemm<R>& g) {
         char why[256];
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (h->prof && !h->dry && g.M > 0 && g.N > 0) {
-            const int idx = (int)h->prof_recs.size() * 2;
-            while ((int)h->ev_pool.size() < idx + 2) {
-                hipEvent_t e;
-                HIPCHECK(hipEventCreate(&e));
-                h->ev_pool.push_back(e);
+        const bool rec = h->prof && !h->dry && g.M > 0 && g.N > 0;
+        if (rec) {
+            // launches inside an H_eff / K_eff matvec are timed per matvec
+            // (one event pair around all its launches), the others one by one
+            int idx = -1;
+            if (h->prof_timed && !h->in_heff) {
+                idx = take_events(h, 2);
+                e0 = h->ev_pool[idx];
+                e1 = h->ev_pool[idx + 1];
             }
-            e0 = h->ev_pool[idx];
-            e1 = h->ev_pool[idx + 1];
             const double fl = 8.0 * g.M * g.N * (double)g.Kin * g.Kout * (double)g.B1 * g.B2;
-            h->prof_recs.push_back({idx, sizeof(R) == 4 ? 1 : 0, fl, h->in_heff});
+            h->prof_recs.push_back({idx, sizeof(R) == 4 ? 1 : 0, fl, h->in_heff, 0, 0,
+                                    h->in_heff ? (int)h->prof_matvecs - 1 : -1});
         }
         Gemm<R> gg = g;
         if (sizeof(R) == 4 && h->split_bf16) gg.split = 1;
         CgemmInfo info;
         if (!cgemm<R>(gg, h->gs, h->stream, why, sizeof(why), e0, e1, &info))
             throw StatusError{TTN_EINVAL, std::string("launch extent check failed: ") + why};
-        if (e0) {
+        if (rec) {
             h->prof_recs.back().kernel = info.kernel;
             h->prof_recs.back().splits = info.splits;
         }
+    }
+};
+
+// Event pair around one Lanczos vector-kernel call inside a profiling
+// window, with the bytes those kernels read and write by construction.
+struct VecTimer {
+    ttn_handle* h;
+    int idx = -1;
+    VecTimer(ttn_handle* hh, double bytes, int64_t n) : h(hh) {
+        if (!h->prof || !h->prof_timed || h->dry) return;
+        idx = take_events(h, 2);
+        h->vec_recs.push_back({idx, bytes, n});
+        (void)hipEventRecord(h->ev_pool[idx], h->stream);
+    }
+    ~VecTimer() {
+        if (idx >= 0) (void)hipEventRecord(h->ev_pool[idx + 1], h->stream);
     }
 };
 
@@ -696,23 +740,44 @@ void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
 void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, const int* skip,
                    bool force_fp64 = false, bool staged = false) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
+    // marks the contraction launches of one matvec; in a timed profiling
+    // window one event pair brackets them (no events between its launches)
     struct HeffMark {
         ttn_handle* h;
+        int idx = -1;
+        size_t first = 0;
         explicit HeffMark(ttn_handle* hh) : h(hh) {
-            h->in_heff = true;
             if (h->prof) h->prof_matvecs += 1;
+            if (h->prof && h->prof_timed && !h->dry) {
+                idx = take_events(h, 2);
+                first = h->prof_recs.size();
+                (void)hipEventRecord(h->ev_pool[idx], h->stream);
+            }
+            h->in_heff = true;
         }
-        ~HeffMark() { h->in_heff = false; }
-    } mark(h);
+        ~HeffMark() {
+            h->in_heff = false;
+            if (idx >= 0) {
+                (void)hipEventRecord(h->ev_pool[idx + 1], h->stream);
+                double fl = 0;
+                for (size_t i = first; i < h->prof_recs.size(); ++i) fl += h->prof_recs[i].flops;
+                h->mv_recs.push_back({idx, fl});
+            }
+        }
+    };
     if (h->prec == TTN_PREC_FP32 && !force_fp64) {
         Ctx<float> c{h, skip};
         if (!staged) convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
-        apply_op<float>(c, o, h->Lf, o.Rb ? h->Rf : nullptr, o.Bb ? h->Bf : nullptr,
-                        o.Wb ? h->Wf : nullptr, h->Xf, h->Yf);
+        {
+            HeffMark mark(h);
+            apply_op<float>(c, o, h->Lf, o.Rb ? h->Rf : nullptr, o.Bb ? h->Bf : nullptr,
+                            o.Wb ? h->Wf : nullptr, h->Xf, h->Yf);
+        }
         if (!staged) convert_f2d(h->Yf, y, 2 * n, skip, h->stream);
     } else {
         Ctx<double> c{h, skip};
         copy_d(x, h->X, 2 * n, skip, h->stream);
+        HeffMark mark(h);
         apply_op<double>(c, o, o.Lb, o.Rb, o.Bb, o.Wb, h->X, y);
     }
 }
@@ -737,7 +802,12 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     // mixed precision: the Lanczos kernels write the FP32 input of the next
     // matvec and widen its FP32 output themselves
     float* xf = (h->prec == TTN_PREC_FP32 && n > LZ_SMALL_N) ? h->Xf : nullptr;
-    lz_start(x, n, h->Vk, lz, h->red, nb, s, h->nonherm ? 1 : 0, xf);
+    // bytes per call: 16 per complex FP64 element, 8 per FP32 element
+    const double E = 16.0 * (double)n, Ef = xf ? 8.0 * (double)n : 0.0;
+    {
+        VecTimer t(h, 3 * E + Ef, n);   // norm of x, then v0 = x / |x| (+ its FP32 copy)
+        lz_start(x, n, h->Vk, lz, h->red, nb, s, h->nonherm ? 1 : 0, xf);
+    }
     if (n <= LZ_SMALL_N) {
         for (int j = 0; j < h->m; ++j) {
             apply_op_prec(h, o, h->Vk + 2 * n * j, h->W, &lz->done);
@@ -754,11 +824,23 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
         apply_op_prec(h, o, vj, h->W, &lz->done, false, xf != nullptr);
         // classical Gram-Schmidt, two passes: the first projection also gives alpha_j
         const bool last = j == h->m - 1;
-        lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s, xf ? h->Yf : nullptr, last || !fuse);
+        const double kc = j + 1;
+        {
+            // V^H w over j + 1 vectors; w read, or widened from the FP32 matvec output
+            VecTimer t(h, kc * E + (xf ? 0.5 * E + E : E), n);
+            lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s, xf ? h->Yf : nullptr, last || !fuse);
+        }
         if (last) break;
-        lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s, fuse);
-        lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s, xf,
-                         fuse);
+        {
+            VecTimer t(h, kc * E + 2 * E, n);   // w -= V c and V^H w in one pass (w read and written)
+            lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s, fuse);
+        }
+        {
+            // w -= V c' with |w|^2, then v_{j+1} = w / beta_j (+ its FP32 copy)
+            VecTimer t(h, kc * E + 2 * E + 2 * E + Ef, n);
+            lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s,
+                             xf, fuse);
+        }
     }
 }
 
@@ -793,6 +875,7 @@ void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
     }
     lanczos_basis(h, o, x);
     lz_expm(h->lz, tau, h->st, h->stream);
+    VecTimer t(h, 16.0 * (double)n * (h->m + 1), n);   // x = |x| V y: m basis vectors read, x written
     lz_combine(h->Vk, n, x, h->lz, h->stream);
 }
 
@@ -1142,12 +1225,21 @@ void step_body(ttn_handle* h, double tau) {
     sweep_bwd(h, tau);
 }
 
-// Adds the device time of every recorded launch to `out`.
-void accumulate_prof(const std::vector<ttn_handle::ProfRec>& recs, const std::vector<hipEvent_t>& pool,
-                     ttn_profile* out) {
-    for (const auto& r : recs) {
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, pool[r.ev], pool[r.ev + 1]));
+// Device time of one individually timed contraction launch (its main kernel
+// and split-K reduction between two events); -1 for launches timed per matvec.
+double launch_ms(const ttn_handle::ProfRec& r, const std::vector<hipEvent_t>& pool) {
+    if (r.ev < 0) return -1.0;
+    float a = 0.f;
+    HIPCHECK(hipEventElapsedTime(&a, pool[r.ev], pool[r.ev + 1]));
+    return (double)a;
+}
+
+// Adds the launches, flops and device times of a window to `out`: launches
+// outside H_eff / K_eff matvecs carry their own event time; the matvec
+// launches are timed together, per matvec.
+void accumulate_prof(const ttn_handle* h, ttn_profile* out) {
+    for (const auto& r : h->prof_recs) {
+        const double ms = r.ev >= 0 ? launch_ms(r, h->ev_pool) : 0.0;
         ttn_kernel_prof& k = r.prec ? out->gemm_f32 : out->gemm_f64;
         k.launches += 1;
         k.ms += ms;
@@ -1159,9 +1251,15 @@ void accumulate_prof(const std::vector<ttn_handle::ProfRec>& recs, const std::ve
         }
         if (r.heff) {
             out->heff.launches += 1;
-            out->heff.ms += ms;
             out->heff.flops += r.flops;
         }
+    }
+    for (const auto& m : h->mv_recs) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, h->ev_pool[m.ev], h->ev_pool[m.ev + 1]));
+        out->heff.ms += ms;
+        // the matvec launches' share of their precision class
+        (h->prec == TTN_PREC_FP64 ? out->gemm_f64 : out->gemm_f32).ms += ms;
     }
 }
 
@@ -1569,18 +1667,6 @@ int ttn_workspace_query(const ttn_config* cfg, size_t* device_bytes) {
     }
 }
 
-// True when the process runs under rocprofv3 hardware-counter collection
-// (--pmc or a counter input file), which hands its counter list to the
-// profiled process in ROCPROF_COUNTERS.  Step graphs are then not used: a
-// counter pass that captured and replayed the step graph ended in a
-// segmentation fault inside the HIP runtime, while the same graphs replay
-// correctly without counter collection and the same steps launched eagerly
-// run correctly under it.
-bool counter_collection_attached() {
-    const char* c = std::getenv("ROCPROF_COUNTERS");
-    return c && *c;
-}
-
 int ttn_init(const ttn_config* cfg, void* d_workspace, size_t bytes, void* hip_stream, ttn_handle** out) {
     if (!out) return TTN_EINVAL;
     *out = nullptr;
@@ -1590,7 +1676,6 @@ int ttn_init(const ttn_config* cfg, void* d_workspace, size_t bytes, void* hip_s
         if (!d_workspace) return TTN_EINVAL;
         h = new ttn_handle();
         h->stream = (hipStream_t)hip_stream;
-        h->use_graphs = !counter_collection_attached();
         setup_config(h, cfg);
         Bump b(d_workspace, bytes, &h->regions);
         plan(h, b);
@@ -1990,9 +2075,19 @@ int ttn_profile_begin(ttn_handle* h) {
     if (!h) return TTN_EINVAL;
     if (h->poisoned) return TTN_ESTATE;
     h->prof = true;
+    h->prof_timed = true;
     h->prof_recs.clear();
+    h->vec_recs.clear();
+    h->mv_recs.clear();
+    h->ev_used = 0;
     h->prof_matvecs = 0;
     return TTN_OK;
+}
+
+int ttn_profile_begin_untimed(ttn_handle* h) {
+    const int rc = ttn_profile_begin(h);
+    if (rc == TTN_OK) h->prof_timed = false;
+    return rc;
 }
 
 int ttn_profile_end(ttn_handle* h, ttn_profile* out) {
@@ -2001,19 +2096,31 @@ int ttn_profile_end(ttn_handle* h, ttn_profile* out) {
     try {
         sync(h);
         std::memset(out, 0, sizeof(*out));
-        accumulate_prof(h->prof_recs, h->ev_pool, out);
+        accumulate_prof(h, out);
         out->matvecs = h->prof_matvecs;
         h->prof_last.clear();
-        for (const auto& r : h->prof_recs) {
+        for (const auto& r : h->prof_recs)
+            h->prof_last.push_back(ttn_launch_rec{r.kernel, r.prec, r.heff ? 1 : 0, r.splits, r.matvec, 0, r.flops,
+                                                  launch_ms(r, h->ev_pool)});
+        for (const auto& r : h->vec_recs) {
             float ms = 0.f;
             HIPCHECK(hipEventElapsedTime(&ms, h->ev_pool[r.ev], h->ev_pool[r.ev + 1]));
-            h->prof_last.push_back(ttn_launch_rec{r.kernel, r.prec, r.heff ? 1 : 0, r.splits, r.flops, (double)ms});
+            for (ttn_vec_prof* p : {&out->lanczos, r.n >= (1 << 20) ? &out->lanczos_large : nullptr}) {
+                if (!p) continue;
+                p->calls += 1;
+                p->ms += ms;
+                p->bytes += r.bytes;
+            }
         }
         h->prof = false;
         h->prof_recs.clear();
+        h->vec_recs.clear();
+        h->mv_recs.clear();
         return TTN_OK;
     } catch (const StatusError& e) {
         h->prof = false;
+        h->vec_recs.clear();
+        h->mv_recs.clear();
         return fail(h, e);
     }
 }
@@ -2122,7 +2229,7 @@ int ttn_sample(ttn_handle* h, int64_t n_shots, uint64_t seed, int64_t shot0, voi
 
 int ttn_set_graphs(ttn_handle* h, int32_t enabled) {
     if (!h) return TTN_EINVAL;
-    h->use_graphs = enabled != 0 && !counter_collection_attached();
+    h->use_graphs = enabled != 0;
     return TTN_OK;
 }
 

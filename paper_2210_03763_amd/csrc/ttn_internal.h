@@ -59,7 +59,8 @@ struct CgemmInfo {
 
 // Validates every operand extent against the region table and launches.
 // Returns false (and launches nothing) when an operand would leave its
-// region; `why` receives a description.
+// region; `why` receives a description.  ev_begin / ev_end (optional) are
+// recorded before the main kernel and after its split-K reduction.
 template <typename R>
 bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, int whylen,
            hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr, CgemmInfo* info = nullptr);

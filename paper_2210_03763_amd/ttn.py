@@ -47,14 +47,19 @@ class KernelProf(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double)]
 
 
+class VecProf(C.Structure):
+    _fields_ = [("calls", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double)]
+
+
 class Profile(C.Structure):
     _fields_ = [("gemm_f32", KernelProf), ("gemm_f64", KernelProf), ("heff", KernelProf),
-                ("matvecs", C.c_int64), ("gemm_bf16x3", KernelProf)]
+                ("matvecs", C.c_int64), ("gemm_bf16x3", KernelProf), ("lanczos", VecProf),
+                ("lanczos_large", VecProf)]
 
 
 class LaunchRec(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("prec", C.c_int32), ("heff", C.c_int32), ("splits", C.c_int32),
-                ("flops", C.c_double), ("ms", C.c_double)]
+                ("matvec", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double), ("ms", C.c_double)]
 
 
 _lib = None
@@ -93,6 +98,7 @@ def lib():
             "ttn_record_begin": (C.c_int, [P, I32, I32, P, C.c_size_t]),
             "ttn_backward": (C.c_int, [P, I32, IP, D, DP, DP]),
             "ttn_profile_begin": (C.c_int, [P]),
+            "ttn_profile_begin_untimed": (C.c_int, [P]),
             "ttn_profile_end": (C.c_int, [P, C.POINTER(Profile)]),
             "ttn_profile_launches": (I64, [P, C.POINTER(LaunchRec), I64]),
             "ttn_destroy": (C.c_int, [P]),
@@ -244,10 +250,11 @@ class TTN:
         self._check(lib().ttn_overlap(self.h, other.h, _dptr(out)), self.h)
         return complex(out[0], out[1])
 
-    def profile_begin(self):
-        """Open a profiling window (every contraction launch bracketed by HIP
-        events on the handle's stream; launches run eagerly)."""
-        self._check(lib().ttn_profile_begin(self.h), self.h)
+    def profile_begin(self, timed: bool = True):
+        """Open a profiling window (launches run eagerly and are recorded;
+        timed: with HIP events per matvec and per other launch)."""
+        f = lib().ttn_profile_begin if timed else lib().ttn_profile_begin_untimed
+        self._check(f(self.h), self.h)
 
     def profile_end(self) -> Profile:
         """Close the window: per-class launch counts, event times, flops."""
@@ -261,8 +268,8 @@ class TTN:
         self._check(n, self.h)
         arr = (LaunchRec * max(1, n))()
         lib().ttn_profile_launches(self.h, arr, n)
-        return [dict(kernel=r.kernel, prec=r.prec, heff=r.heff, splits=r.splits, flops=r.flops, ms=r.ms)
-                for r in arr[:n]]
+        return [dict(kernel=r.kernel, prec=r.prec, heff=r.heff, splits=r.splits, matvec=r.matvec, flops=r.flops,
+                     ms=r.ms) for r in arr[:n]]
 
     def set_graphs(self, enabled: bool):
         """Replay the step body as a HIP graph (default) or launch eagerly."""

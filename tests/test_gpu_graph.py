@@ -40,21 +40,21 @@ def test_graph_replays_equal_eager_steps(name):
 
 
 def test_profile_window_with_graph_replays():
-    import ctypes as C
-    import bench
-    L = T.lib()
-    L.ttn_profile_begin.argtypes = [C.c_void_p]
-    L.ttn_profile_end.argtypes = [C.c_void_p, C.POINTER(bench.Profile)]
     w = W.config("c1-ent").copy(precision=T.PREC_FP32)
     res = []
     for graphs in (True, False):
         g = T.TTN(w)
         g.set_graphs(graphs)
         g.step(1)
-        assert L.ttn_profile_begin(g.h) == 0
+        g.profile_begin()
         g.step(2)
-        p = bench.Profile()
-        assert L.ttn_profile_end(g.h, C.byref(p)) == 0
+        p = g.profile_end()
+        recs = g.profile_launches()
+        assert len(recs) == p.gemm_f32.launches + p.gemm_f64.launches
+        # matvec launches are timed per matvec (ms -1 each), the rest one by one
+        assert all((r["ms"] < 0) == (r["heff"] == 1) for r in recs)
+        single = sum(r["ms"] for r in recs if r["ms"] >= 0)
+        assert abs(single + p.heff.ms - (p.gemm_f32.ms + p.gemm_f64.ms)) < 1e-6 * max(1.0, p.gemm_f32.ms)
         res.append(p)
         g.close()
     a, b = res
