@@ -570,7 +570,7 @@ class OracleTTN:
         since the last reset of qr_min: the conditioning of the step's gauge
         moves (a diagnostic; it changes no arithmetic)."""
         Q, R = qr_toward(T, leg)
-        self.qr_min = min(self.qr_min, float(torch.diagonal(R).real.min()))
+        self.qr_min = min(self.qr_min, float(torch.diagonal(R).real.min().detach()))
         return Q, R
 
     def _visit_fwd(self, v, tau):
