@@ -247,6 +247,23 @@ int ttn_leg_contract(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int
                      const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y, int32_t sum_ops,
                      int32_t accumulate, void* hip_stream);
 
+/* ttn_leg_contract without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, checks and result as
+ * ttn_leg_contract (the same kernels and split factors, so the same bits),
+ * but the split-K partial sums live in a file-scope device array of
+ * 64 MiB that every GPU the library runs on holds until the process ends,
+ * and the call only enqueues: it does not synchronise the stream (errors of
+ * the kernels show at the caller's next synchronisation).  No input exceeds
+ * the array: the split factor is capped so that the partial sums fit, and
+ * split-free launches need none.  Every call on one GPU shares that GPU's
+ * array, so calls that may overlap on one GPU (different streams without
+ * ordering) race; calls on one stream are ordered.  The array's address is
+ * looked up once per device, on the first call with that device current. */
+int ttn_leg_contract_noalloc(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int32_t DP,
+                             int32_t n_ops, const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y,
+                             int32_t sum_ops, int32_t accumulate, void* hip_stream);
+
 /* Device time of the contraction kernels inside a profiling window. */
 typedef struct {
     int64_t launches;       /* kernel launches                                  */

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2014,56 +2015,114 @@ int64_t ttn_export_state(ttn_handle* h, double* host, int64_t len) {
     }
 }
 
+namespace {
+
+// Checks the arguments of a leg contraction and enqueues it on `stream`, with
+// `partial` (bytes) as split-K scratch.  Throws StatusError.
+void leg_contract_enqueue(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int32_t DP, int32_t n_ops,
+                          const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y, int32_t sum_ops,
+                          int32_t accumulate, hipStream_t stream, void* partial, int64_t bytes) {
+    if (precision != TTN_PREC_FP64 && precision != TTN_PREC_FP32 && precision != TTN_PREC_BF16X3)
+        throw StatusError{TTN_EINVAL, "bad precision"};
+    if (leg < 0 || leg > 2 || DL < 1 || DR < 1 || DP < 1 || n_ops < 1 || !d_ops || !d_x || !d_y)
+        throw StatusError{TTN_EINVAL, "bad leg, dimensions or pointers"};
+    if (sum_ops && !x_per_op) throw StatusError{TTN_EINVAL, "sum_ops requires x_per_op"};
+    const int D = leg == 0 ? DL : (leg == 1 ? DR : DP);
+    const int64_t n = (int64_t)DL * DR * DP, D2 = (int64_t)D * D;
+    const size_t esz = precision == TTN_PREC_FP64 ? 8 : 4;
+    ttn_handle h;
+    h.stream = stream;
+    h.split_bf16 = precision == TTN_PREC_BF16X3;
+    // operand regions come from the argument sizes
+    const int nx = x_per_op ? n_ops : 1, ny = sum_ops ? 1 : n_ops;
+    h.regions.push_back(Region{(uintptr_t)d_ops, (uintptr_t)d_ops + 2 * D2 * n_ops * esz});
+    h.regions.push_back(Region{(uintptr_t)d_x, (uintptr_t)d_x + 2 * n * nx * esz});
+    h.regions.push_back(Region{(uintptr_t)d_y, (uintptr_t)d_y + 2 * n * ny * esz});
+    h.gs.partial = partial;
+    h.gs.bytes = bytes;
+    sort_regions(&h);
+    if (precision != TTN_PREC_FP64) {
+        Ctx<float> c{&h, nullptr};
+        if (sum_ops)
+            leg_apply_sum<float>(c, leg, (const float*)d_ops, 2 * D2, (const float*)d_x, 2 * n, (float*)d_y, DL, DR,
+                                 DP, n_ops, accumulate ? 1 : 0);
+        else
+            leg_apply<float>(c, leg, (const float*)d_ops, 2 * D2, (const float*)d_x, x_per_op ? 2 * n : 0,
+                             (float*)d_y, 2 * n, DL, DR, DP, n_ops, accumulate ? 1 : 0);
+    } else {
+        Ctx<double> c{&h, nullptr};
+        if (sum_ops)
+            leg_apply_sum<double>(c, leg, (const double*)d_ops, 2 * D2, (const double*)d_x, 2 * n, (double*)d_y,
+                                  DL, DR, DP, n_ops, accumulate ? 1 : 0);
+        else
+            leg_apply<double>(c, leg, (const double*)d_ops, 2 * D2, (const double*)d_x, x_per_op ? 2 * n : 0,
+                              (double*)d_y, 2 * n, DL, DR, DP, n_ops, accumulate ? 1 : 0);
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+// Split-K scratch of the allocating entry point, and the size of the
+// file-scope array of the no-allocation one: the same size, so that both
+// choose the same split factors and give the same bits.
+constexpr int64_t LEG_SCRATCH_BYTES = (int64_t)64 << 20;
+
+// Split-K scratch of ttn_leg_contract_noalloc: every GPU the library runs on
+// holds one copy until the process ends.  Host code never uses this name as
+// an address; it uses the per-device pointer from hipGetSymbolAddress below.
+static __device__ __align__(256) unsigned char scratch[LEG_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's address of `scratch`, looked up once per device with
+// that device current.
+void* scratch_for_current_device() {
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) throw StatusError{TTN_EDEVICE, "device ordinal out of range"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            throw StatusError{TTN_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 int ttn_leg_contract(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int32_t DP, int32_t n_ops,
                      const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y, int32_t sum_ops,
                      int32_t accumulate, void* hip_stream) {
+    void* partial = nullptr;
     try {
-        if (precision != TTN_PREC_FP64 && precision != TTN_PREC_FP32 && precision != TTN_PREC_BF16X3)
-            return TTN_EINVAL;
-        if (leg < 0 || leg > 2 || DL < 1 || DR < 1 || DP < 1 || n_ops < 1 || !d_ops || !d_x || !d_y)
-            return TTN_EINVAL;
-        if (sum_ops && !x_per_op) return TTN_EINVAL;
-        const int D = leg == 0 ? DL : (leg == 1 ? DR : DP);
-        const int64_t n = (int64_t)DL * DR * DP, D2 = (int64_t)D * D;
-        const size_t esz = precision == TTN_PREC_FP64 ? 8 : 4;
-        ttn_handle h;
-        h.stream = (hipStream_t)hip_stream;
-        h.split_bf16 = precision == TTN_PREC_BF16X3;
-        // operand regions come from the argument sizes; split-K scratch is
-        // allocated here for this call
-        const int nx = x_per_op ? n_ops : 1, ny = sum_ops ? 1 : n_ops;
-        h.regions.push_back(Region{(uintptr_t)d_ops, (uintptr_t)d_ops + 2 * D2 * n_ops * esz});
-        h.regions.push_back(Region{(uintptr_t)d_x, (uintptr_t)d_x + 2 * n * nx * esz});
-        h.regions.push_back(Region{(uintptr_t)d_y, (uintptr_t)d_y + 2 * n * ny * esz});
-        h.gs.bytes = (int64_t)64 << 20;
-        HIPCHECK(hipMalloc(&h.gs.partial, h.gs.bytes));
-        sort_regions(&h);
-        try {
-            if (precision != TTN_PREC_FP64) {
-                Ctx<float> c{&h, nullptr};
-                if (sum_ops)
-                    leg_apply_sum<float>(c, leg, (const float*)d_ops, 2 * D2, (const float*)d_x, 2 * n, (float*)d_y,
-                                         DL, DR, DP, n_ops, accumulate ? 1 : 0);
-                else
-                    leg_apply<float>(c, leg, (const float*)d_ops, 2 * D2, (const float*)d_x, x_per_op ? 2 * n : 0,
-                                     (float*)d_y, 2 * n, DL, DR, DP, n_ops, accumulate ? 1 : 0);
-            } else {
-                Ctx<double> c{&h, nullptr};
-                if (sum_ops)
-                    leg_apply_sum<double>(c, leg, (const double*)d_ops, 2 * D2, (const double*)d_x, 2 * n,
-                                          (double*)d_y, DL, DR, DP, n_ops, accumulate ? 1 : 0);
-                else
-                    leg_apply<double>(c, leg, (const double*)d_ops, 2 * D2, (const double*)d_x, x_per_op ? 2 * n : 0,
-                                      (double*)d_y, 2 * n, DL, DR, DP, n_ops, accumulate ? 1 : 0);
-            }
-            HIPCHECK(hipGetLastError());
-            HIPCHECK(hipStreamSynchronize(h.stream));
-        } catch (...) {
-            (void)hipStreamSynchronize(h.stream);
-            (void)hipFree(h.gs.partial);
-            throw;
+        const hipStream_t st = (hipStream_t)hip_stream;
+        HIPCHECK(hipMalloc(&partial, LEG_SCRATCH_BYTES));
+        leg_contract_enqueue(precision, leg, DL, DR, DP, n_ops, d_ops, d_x, x_per_op, d_y, sum_ops, accumulate, st,
+                             partial, LEG_SCRATCH_BYTES);
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipFree(partial));
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        if (partial) {
+            (void)hipStreamSynchronize((hipStream_t)hip_stream);
+            (void)hipFree(partial);
         }
-        HIPCHECK(hipFree(h.gs.partial));
+        g_init_error = e.msg;
+        return e.code;
+    }
+}
+
+int ttn_leg_contract_noalloc(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int32_t DP, int32_t n_ops,
+                             const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y, int32_t sum_ops,
+                             int32_t accumulate, void* hip_stream) {
+    try {
+        void* partial = scratch_for_current_device();
+        leg_contract_enqueue(precision, leg, DL, DR, DP, n_ops, d_ops, d_x, x_per_op, d_y, sum_ops, accumulate,
+                             (hipStream_t)hip_stream, partial, LEG_SCRATCH_BYTES);
         return TTN_OK;
     } catch (const StatusError& e) {
         g_init_error = e.msg;
