@@ -68,6 +68,20 @@ extern "C" {
 #define TTN_PREC_FP32 1
 #define TTN_PREC_BF16X3 2
 
+/* Update scheme of the sweep (Sec. "Tensor network simulations": TDVP with
+ * a two-tensor update).  TTN_UPDATE_ONE_SITE: single-site TDVP at fixed bond
+ * dimensions.  TTN_UPDATE_TWO_SITE: every edge (v, parent u) is evolved as
+ * the merged tensor Theta[l, r, s, p] = sum_k T_v[l, r, k] T_u[k, s, p] under
+ * its two-site effective Hamiltonian and split back, truncated to the edge's
+ * link dimension by the largest singular values (computed from the smaller
+ * Gram matrix Theta^H Theta or Theta Theta^H with a Jacobi eigensolver), the
+ * kept values rescaled to the norm of Theta; nodes between the updates of the
+ * edges that meet there are evolved backward.  FP64 only, closed systems
+ * only, N >= 4, and the smaller side of every merged tensor (min(D_l D_r,
+ * D_s D_p)) at most 256 (TTN_ENOTSUP otherwise); no adjoint. */
+#define TTN_UPDATE_ONE_SITE 0
+#define TTN_UPDATE_TWO_SITE 1
+
 typedef struct ttn_handle ttn_handle;
 
 typedef struct {
@@ -76,7 +90,7 @@ typedef struct {
     int32_t chi;            /* maximal bond dimension, 1 <= chi <= 256        */
     int32_t krylov_dim;     /* Lanczos dimension m, 1 <= m <= 16              */
     int32_t precision;      /* TTN_PREC_*                                     */
-    int32_t reserved;
+    int32_t update;         /* TTN_UPDATE_* (0: single-site)                  */
     double c6;              /* van der Waals coefficient (a = 1 units)         */
     double r_cut;           /* pairs farther than r_cut dropped; <= 0: all     */
     double leak_ratio;      /* |r>-|leak> coupling relative to Omega/2 (d = 4) */
@@ -101,6 +115,9 @@ typedef struct {
     double min_r_diag;      /* smallest R_kk of every QR in the step           */
     int32_t min_krylov;     /* smallest Krylov dimension reached (breakdown)   */
     int32_t reserved;
+    double max_discarded;   /* two-site update: largest discarded weight
+                               (dropped share of |Theta|^2) of the step's
+                               splits; 0 for the single-site update          */
 } ttn_step_stats;
 
 /* Device bytes the caller must provide to ttn_init for this configuration
@@ -263,6 +280,16 @@ int ttn_leg_contract(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int
 int ttn_leg_contract_noalloc(int32_t precision, int32_t leg, int32_t DL, int32_t DR, int32_t DP,
                              int32_t n_ops, const void* d_ops, const void* d_x, int32_t x_per_op, void* d_y,
                              int32_t sum_ops, int32_t accumulate, void* hip_stream);
+
+/* The eigensolver of the two-site split on caller memory (kernel unit
+ * tests): eigenvalues and eigenvectors of the Hermitian n x n matrix d_a
+ * (planar complex FP64, column-major; destroyed), 1 <= n <= 256, by the
+ * cyclic Jacobi method with round-robin pair ordering in one workgroup.
+ * d_w[k] receives the k-th largest eigenvalue, d_order[k] (int32) the
+ * column of d_v (n x n planar) holding its eigenvector.  Synchronises
+ * hip_stream; TTN_ENUMERIC if the iteration does not converge, TTN_EINVAL
+ * for bad arguments.  Allocates a small status block. */
+int ttn_herm_eig(int32_t n, void* d_a, void* d_v, void* d_w, void* d_order, void* hip_stream);
 
 /* Device time of the contraction kernels inside a profiling window. */
 typedef struct {

@@ -71,6 +71,7 @@ struct ttn_handle {
     double gamma = 0;       // Rydberg decay rate (open system); > 0 selects Arnoldi
     bool split_bf16 = false; // BF16x3 products in the FP32 contractions
     bool nonherm = false;
+    bool two_site = false;   // two-tensor TDVP update with truncated splits
     hipStream_t stream = nullptr;
     std::string err;
     bool poisoned = false;
@@ -98,6 +99,11 @@ struct ttn_handle {
     GemmScratch gs;
     double *ov_vec = nullptr, *ov_leaf = nullptr, *ov_M = nullptr, *ov_Y1 = nullptr, *ov_Y2 = nullptr;
     double* opbuf = nullptr;
+    // two-site update: merged tensor, Gram matrix, its eigenvectors and
+    // eigenvalues (descending) with their column order, split factors
+    int64_t n2max = 0, ngmax = 0, mkmax = 0;
+    double *Th = nullptr, *G2 = nullptr, *EV = nullptr, *ew = nullptr, *MV = nullptr, *Cm = nullptr;
+    int* eorder = nullptr;
     // program
     int n_seg = 0;
     std::vector<double> edges;
@@ -211,6 +217,33 @@ inline bool is_bottom(const ttn_handle* h, int v) { return h->level[v] == 0; }
 inline int leg_in_parent(const ttn_handle* h, int v) { return h->idx[v] & 1; }
 inline int sites_left(const ttn_handle* h, int v) { return h->scount[v] / 2; }
 
+// The edge between v and its parent u, as the two-site update sees it: the
+// merged tensor Theta[l, r, s, p] (l, r the legs of v's children, s the leg
+// of v's sibling in u, p u's parent leg), matricised as (l r) x (s p), m x n,
+// split back with k = the link dimension of the edge.
+struct Edge2 {
+    int u, leg, sib;
+    int DL, DR, DS, DP, k;
+    int sL, sR, sS;     // sites below v's left child, right child, the sibling
+    int64_t m, n;
+};
+Edge2 edge2(const ttn_handle* h, int v) {
+    Edge2 e;
+    e.u = h->parent[v];
+    e.leg = leg_in_parent(h, v);
+    e.sib = e.leg == 0 ? h->ch1[e.u] : h->ch0[e.u];
+    e.DL = h->DL[v];
+    e.DR = h->DR[v];
+    e.k = h->DP[v];
+    e.DS = e.leg == 0 ? h->DR[e.u] : h->DL[e.u];
+    e.DP = h->DP[e.u];
+    e.sL = e.sR = sites_left(h, v);
+    e.sS = h->scount[v];
+    e.m = (int64_t)e.DL * e.DR;
+    e.n = (int64_t)e.DS * e.DP;
+    return e;
+}
+
 // plan every buffer; with ws == nullptr only sizes are accumulated
 void plan(ttn_handle* h, Bump& b) {
     const int nn = h->n_nodes;
@@ -244,15 +277,38 @@ void plan(ttn_handle* h, Bump& b) {
     // bond stacks (sites below v, size DP^2) are bounded by stack_max as well
     for (int v = 0; v < nn; ++v)
         h->stack_max = std::max(h->stack_max, (int64_t)(1 + h->scount[v]) * h->DP[v] * h->DP[v]);
+    // two-site: merged tensors of every edge, their matvec stacks
+    // [X, U_i, Z_j, V_k] and the split factors
+    h->n2max = h->ngmax = h->mkmax = 0;
+    if (h->two_site)
+        for (int v = 0; v < nn; ++v) {
+            if (v == h->root) continue;
+            const Edge2 e = edge2(h, v);
+            h->n2max = std::max(h->n2max, e.m * e.n);
+            h->ngmax = std::max(h->ngmax, std::min(e.m, e.n));
+            h->mkmax = std::max(h->mkmax, std::max(e.m, e.n) * e.k);
+            h->stack_max = std::max(h->stack_max, (int64_t)(1 + e.sL + e.sR + e.sS) * e.m * e.n);
+        }
+    const int64_t nvec = std::max(h->nmax, h->n2max);   // Krylov vectors: nodes and merged tensors
+    const int64_t nqr = std::max(h->nmax, h->mkmax);     // QR scratch: nodes and split factors
     const int64_t D2 = (int64_t)h->Dmax * h->Dmax;
     const int64_t smax = h->max_sites + 1;
     h->leafblk = b.take<double>((int64_t)h->N * 4 * h->d * h->d);
     h->d_leaf_site = b.take<int>(h->N);
     h->X = b.take<double>(2 * h->stack_max);
-    h->W = b.take<double>(2 * h->nmax);
-    h->Vk = b.take<double>(2 * h->nmax * (h->m + 1));
-    h->Qtmp = b.take<double>(2 * h->nmax);
+    h->W = b.take<double>(2 * nvec);
+    h->Vk = b.take<double>(2 * nvec * (h->m + 1));
+    h->Qtmp = b.take<double>(2 * nqr);
     h->Ttmp = b.take<double>(2 * h->nmax);
+    if (h->two_site) {
+        h->Th = b.take<double>(2 * h->n2max);
+        h->G2 = b.take<double>(2 * h->ngmax * h->ngmax);
+        h->EV = b.take<double>(2 * h->ngmax * h->ngmax);
+        h->ew = b.take<double>(h->ngmax);
+        h->eorder = b.take<int>(h->ngmax);
+        h->MV = b.take<double>(2 * h->mkmax);
+        h->Cm = b.take<double>(2 * h->mkmax);
+    }
     if (h->prec == TTN_PREC_FP32) {
         h->Xf = b.take<float>(2 * h->stack_max);
         h->Yf = b.take<float>(2 * h->nmax);
@@ -656,13 +712,31 @@ const double* child_block(ttn_handle* h, int v, int side) {
     return h->up[side == 0 ? h->ch0[v] : h->ch1[v]];
 }
 
-// Operator description of H_eff at node v (or K_eff at the link above v).
+// Two-site effective Hamiltonian of the edge (v, u) on Theta[l, r, s, p]
+// (Edge2), from the environments of the four outer links: the block
+// Hamiltonians H_L, H_R, H_S, H_P on their legs, and every coupling V_ij
+// n_i n_j between sites below different outer links: pairs across l and r,
+// l or r and s (through A'_i = sum_{k below s} V_ik N_k, i below v), and
+// every site below u with the rest of the lattice (W_i on p).
+struct Op2 {
+    Edge2 e;
+    const double* Lb;   // [H_L, N_i (i below l)]
+    const double* Rb;   // [H_R, N_j (j below r)]
+    const double* Bv;   // [H_R, A_i (i below l)], A_i = sum_{j below r} V_ij N_j
+    const double* Sb;   // [H_S, N_k (k below s)]
+    const double* Sa;   // [H_S, A'_i (i below v)], A'_i = sum_{k below s} V_ik N_k
+    const double* Wu;   // [H_P, W_i (i below u, leaf order)], nullptr when u is the root
+};
+
+// Operator description of H_eff at node v (or K_eff at the link above v);
+// with e2 the two-site H_eff of an edge (DL DR DP = the merged tensor size).
 struct OpDesc {
     int DL, DR, DP, sL, sR;
     const double* Lb;   // [H_L, N_i (i in S_L)]      DL x DL each
     const double* Rb;   // [H_R, N_j (j in S_R)]      DR x DR
     const double* Bb;   // [H_R, A_i (i in S_L)]      DR x DR, A_i = sum_j V_ij N_j
     const double* Wb;   // [H_P, W_i (S_L), W_j (S_R)] DP x DP, nullptr at the root
+    const Op2* e2 = nullptr;
 };
 
 // Bstk = [H_R, A_1..A_sL] for node v
@@ -719,6 +793,48 @@ void apply_op(Ctx<R>& c, const OpDesc& o, const R* Lb, const R* Rb, const R* Bb,
     if (Wb) leg_apply_sum<R>(c, 2, Wb, 2 * P2, Xs, sx, Y, DL, DR, DP, 1 + sL + sR, 1);
 }
 
+// Y = H_eff2 X for the merged tensor X[l, r, s, p] (slot 0 of the stack Xs,
+// slot stride 2 m n); the other slots receive U_i = N_i on l, Z_j = N_j on r
+// and V_k = N_k on s.  Slot order [X, U, Z, V] when v is u's left child,
+// [X, V, U, Z] when it is the right one, so that the parent-leg operators
+// of u (leaf order: left subtree of u first) meet their tensors in order.
+// Every leg operation is a leg contraction of a three-leg view:
+// l, r on (DL, DR, DS DP); s, p on (DL DR, DS, DP).
+void apply_op2(Ctx<double>& c, const Op2& o, double* Xs, double* Y) {
+    const Edge2& e = o.e;
+    const int DL = e.DL, DR = e.DR, DS = e.DS, DP = e.DP, sL = e.sL, sR = e.sR, sS = e.sS;
+    const int64_t sx = 2 * e.m * e.n;
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, S2 = (int64_t)DS * DS, P2 = (int64_t)DP * DP;
+    const bool hasP = o.Wu != nullptr;
+    const int oV = e.leg == 0 ? 1 + sL + sR : 1;
+    const int oU = e.leg == 0 ? 1 : 1 + sS;
+    const int oZ = oU + sL;
+    const int DSP = DS * DP, DLR = DL * DR;
+    // l leg: Y = H_L X, U_i = N_i X
+    leg_apply<double>(c, 0, o.Lb, 0, Xs, 0, Y, 0, DL, DR, DSP, 1, 0);
+    leg_apply<double>(c, 0, o.Lb + 2 * L2, 2 * L2, Xs, 0, Xs + oU * sx, sx, DL, DR, DSP, sL, 0);
+    // r leg: Z_j = N_j X
+    leg_apply<double>(c, 1, o.Rb + 2 * R2, 2 * R2, Xs, 0, Xs + oZ * sx, sx, DL, DR, DSP, sR, 0);
+    // s leg: V_k = N_k X (they only feed the parent-leg terms)
+    if (hasP) leg_apply<double>(c, 1, o.Sb + 2 * S2, 2 * S2, Xs, 0, Xs + oV * sx, sx, DLR, DS, DP, sS, 0);
+    // r leg sums: H_R X + sum_i A_i U_i
+    if (oU == 1) {
+        leg_apply_sum<double>(c, 1, o.Bv, 2 * R2, Xs, sx, Y, DL, DR, DSP, 1 + sL, 1);
+    } else {
+        leg_apply_sum<double>(c, 1, o.Bv, 2 * R2, Xs, sx, Y, DL, DR, DSP, 1, 1);
+        leg_apply_sum<double>(c, 1, o.Bv + 2 * R2, 2 * R2, Xs + oU * sx, sx, Y, DL, DR, DSP, sL, 1);
+    }
+    // s leg sums: H_S X + sum_{i below v} A'_i (U_i or Z_i)
+    if (oU == 1) {
+        leg_apply_sum<double>(c, 1, o.Sa, 2 * S2, Xs, sx, Y, DLR, DS, DP, 1 + sL + sR, 1);
+    } else {
+        leg_apply_sum<double>(c, 1, o.Sa, 2 * S2, Xs, sx, Y, DLR, DS, DP, 1, 1);
+        leg_apply_sum<double>(c, 1, o.Sa + 2 * S2, 2 * S2, Xs + oU * sx, sx, Y, DLR, DS, DP, sL + sR, 1);
+    }
+    // p leg sums: H_P X + sum over every site below u of W_i on its tensor
+    if (hasP) leg_apply_sum<double>(c, 2, o.Wu, 2 * P2, Xs, sx, Y, DLR, DS, DP, 1 + sL + sR + sS, 1);
+}
+
 // FP32 copies of an operator's stacks for the mixed-precision matvec
 void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
     const int64_t L2 = (int64_t)o.DL * o.DL, R2 = (int64_t)o.DR * o.DR, P2 = (int64_t)o.DP * o.DP;
@@ -766,6 +882,13 @@ void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, c
             }
         }
     };
+    if (o.e2) {   // two-site update: FP64
+        Ctx<double> c{h, skip};
+        copy_d(x, h->X, 2 * n, skip, h->stream);
+        HeffMark mark(h);
+        apply_op2(c, *o.e2, h->X, y);
+        return;
+    }
     if (h->prec == TTN_PREC_FP32 && !force_fp64) {
         Ctx<float> c{h, skip};
         if (!staged) convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
@@ -863,7 +986,7 @@ bool bond_evolve_fused(const ttn_handle* h, int v) {
 // operators run the whole evolution in one workgroup (FP64 in both modes).
 void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
-    if (evolve_fused(h, o.DL, o.DR, o.DP, o.sL, o.sR, o.Bb != nullptr, o.Wb != nullptr)) {
+    if (!o.e2 && evolve_fused(h, o.DL, o.DR, o.DP, o.sL, o.sR, o.Bb != nullptr, o.Wb != nullptr)) {
         const int64_t L2 = (int64_t)o.DL * o.DL, R2 = (int64_t)o.DR * o.DR, P2 = (int64_t)o.DP * o.DP;
         chk(h, x, 2 * n, "krylov input");
         chk(h, o.Lb, 2 * (1 + o.sL) * L2, "L stack");
@@ -1155,6 +1278,186 @@ void sweep_bwd(ttn_handle* h, double tau) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// two-site (two-tensor) update
+// ---------------------------------------------------------------------------
+// C (M x N, leading dimension ldc) = op(A) op(B) in planar complex FP64:
+// op(A) is A (M x K, ld lda) or, with ta, the conjugate transpose of A (K x M,
+// ld lda); op(B) likewise (tb: B is N x K).
+void zgemm(Ctx<double>& c, int M, int N, int K, const double* A, int64_t lda, int64_t ap, bool ta,
+           const double* B, int64_t ldb, int64_t bp, bool tb, double* C, int64_t ldc, int64_t cp) {
+    Gemm<double> g;
+    g.M = M;
+    g.N = N;
+    g.Kin = K;
+    g.A = A;
+    g.a_plane = ap;
+    g.sam = ta ? lda : 1;
+    g.sak = ta ? 1 : lda;
+    g.conjA = ta;
+    g.B = B;
+    g.b_plane = bp;
+    g.sbk = tb ? ldb : 1;
+    g.sbn = tb ? 1 : ldb;
+    g.conjB = tb;
+    g.C = C;
+    g.c_plane = cp;
+    g.scm = 1;
+    g.scn = ldc;
+    c.run(g);
+}
+
+// Writes the k x n matrix X (X[c, j] at X[c sc + j sj], j = s + DS p,
+// conjugated if conj) into the tensor of u in the layout of the edge's leg:
+// leg 0: T_u[c, s, p]; leg 1: T_u[s, c, p].
+void put_u(ttn_handle* h, const Edge2& e, const double* X, int64_t xplane, int64_t sc, int64_t sj, bool conj) {
+    const int64_t k = e.k, DS = e.DS;
+    const int64_t dc = e.leg == 0 ? 1 : DS, ds = e.leg == 0 ? k : 1;
+    chk(h, h->T[e.u], 2 * k * e.n, "split factor of the parent");
+    copy3(X, xplane, sc, sj, sj * DS, h->T[e.u], k * e.n, dc, ds, k * DS, (int)k, (int)DS, e.DP, conj, h->stream);
+}
+
+// Forward two-site update of the edge (v, parent u):
+// Theta <- exp(-i tau H_eff2) Theta, then the split back into T_v and T_u
+// truncated to the edge's link dimension k: the kept subspace is spanned by
+// the eigenvectors of the k largest eigenvalues of the smaller Gram matrix
+// (Theta^H Theta or Theta Theta^H, i.e. the k largest singular values), the
+// other factor is the projection of Theta on it, rescaled to the norm of the
+// untruncated Theta (the kept and discarded weights are the eigenvalue sums).
+// centre_up: T_v an isometry toward its parent, T_u the centre; else T_u an
+// isometry toward v and T_v the centre.  Rebuilds the environment of the
+// link on the isometry's side.
+void update_edge2(ttn_handle* h, int v, double tau, bool centre_up) {
+    Ctx<double> c{h, nullptr};
+    const Edge2 e = edge2(h, v);
+    const int u = e.u;
+    const int64_t m = e.m, n = e.n, k = e.k, mn = m * n;
+    chk(h, h->Th, 2 * mn, "merged tensor");
+    chk(h, h->T[v], 2 * m * k, "node tensor");
+    chk(h, h->Cm, 2 * k * n, "split factor");
+    chk(h, h->MV, 2 * m * k, "split factor");
+    // Theta = T_v (m x k) times T_u as a k x n matrix
+    const double* Tu = h->T[u];
+    if (e.leg == 1) {   // T_u[s, c, p] -> Cm[c, s + DS p]
+        chk(h, h->T[u], 2 * k * n, "parent tensor");
+        copy3(h->T[u], k * n, e.DS, 1, (int64_t)e.DS * k, h->Cm, k * n, 1, k, k * e.DS, (int)k, e.DS, e.DP, false,
+              h->stream);
+        Tu = h->Cm;
+    }
+    zgemm(c, (int)m, (int)n, (int)k, h->T[v], m, m * k, false, Tu, k, k * n, false, h->Th, m, mn);
+    // the two-site effective Hamiltonian of the edge
+    Op2 o2;
+    o2.e = e;
+    o2.Lb = child_block(h, v, 0);
+    o2.Rb = child_block(h, v, 1);
+    prepare_B(h, c, v, o2.Rb, e.DR, e.sL, e.sR);
+    o2.Bv = h->Bstk;
+    o2.Sb = h->up[e.sib];
+    const int64_t S2 = (int64_t)e.DS * e.DS;
+    chk(h, h->Astk, 2 * (1 + e.sL + e.sR) * S2, "sibling coupling stack");
+    copy_d(o2.Sb, h->Astk, 2 * S2, nullptr, h->stream);
+    vsum_stack(c, o2.Sb, e.DS, e.sS, e.leg == 0 ? h->vRL[u] : h->vLR[u], e.sL + e.sR, h->Astk + 2 * S2);
+    o2.Sa = h->Astk;
+    o2.Wu = u == h->root ? nullptr : h->dn[u];
+    OpDesc o{};
+    o.DL = (int)m;
+    o.DR = e.DS;
+    o.DP = e.DP;
+    o.e2 = &o2;
+    lanczos_expm(h, o, h->Th, tau);
+    // the split
+    const int64_t ng = std::min(m, n);
+    chk(h, h->G2, 2 * ng * ng, "Gram matrix");
+    chk(h, h->EV, 2 * ng * ng, "eigenvectors");
+    chk(h, h->ew, ng, "eigenvalues");
+    if (n <= m) {
+        zgemm(c, (int)n, (int)n, (int)m, h->Th, m, mn, true, h->Th, m, mn, false, h->G2, n, n * n);   // Theta^H Theta
+        herm_eig(h->G2, (int)n, h->EV, h->ew, h->eorder, h->st, h->stream);
+        gather_cols(h->EV, (int)n, h->eorder, (int)k, h->Cm, h->stream);   // V_k (n x k)
+        if (centre_up) {
+            zgemm(c, (int)m, (int)k, (int)n, h->Th, m, mn, false, h->Cm, n, n * k, false, h->MV, m, m * k);
+            qr_toward(h, (int)m, 1, (int)k, h->MV, 2, h->Rq);   // T_v = orth(Theta V_k)
+            copy_d(h->MV, h->T[v], 2 * m * k, nullptr, h->stream);
+            zgemm(c, (int)k, (int)n, (int)m, h->MV, m, m * k, true, h->Th, m, mn, false, h->Ttmp, k, k * n);
+            chk(h, h->Ttmp, 2 * k * n, "split factor");
+            put_u(h, e, h->Ttmp, k * n, 1, k, false);                  // T_u = T_v^H Theta
+            split_finish(h->ew, (int)n, (int)k, h->T[u], k * n, h->st, h->stream);
+        } else {
+            zgemm(c, (int)m, (int)k, (int)n, h->Th, m, mn, false, h->Cm, n, n * k, false, h->T[v], m, m * k);
+            put_u(h, e, h->Cm, n * k, n, 1, true);                     // T_u = V_k^H
+            split_finish(h->ew, (int)n, (int)k, h->T[v], m * k, h->st, h->stream);
+        }
+    } else {
+        zgemm(c, (int)m, (int)m, (int)n, h->Th, m, mn, false, h->Th, m, mn, true, h->G2, m, m * m);   // Theta Theta^H
+        herm_eig(h->G2, (int)m, h->EV, h->ew, h->eorder, h->st, h->stream);
+        gather_cols(h->EV, (int)m, h->eorder, (int)k, h->MV, h->stream);   // U_k (m x k)
+        if (centre_up) {
+            copy_d(h->MV, h->T[v], 2 * m * k, nullptr, h->stream);
+            zgemm(c, (int)k, (int)n, (int)m, h->MV, m, m * k, true, h->Th, m, mn, false, h->Ttmp, k, k * n);
+            chk(h, h->Ttmp, 2 * k * n, "split factor");
+            put_u(h, e, h->Ttmp, k * n, 1, k, false);                  // T_u = U_k^H Theta
+            split_finish(h->ew, (int)m, (int)k, h->T[u], k * n, h->st, h->stream);
+        } else {
+            zgemm(c, (int)n, (int)k, (int)m, h->Th, m, mn, true, h->MV, m, m * k, false, h->Cm, n, n * k);
+            qr_toward(h, (int)n, 1, (int)k, h->Cm, 2, h->Rq);        // Q = orth(Theta^H U_k)
+            zgemm(c, (int)m, (int)k, (int)n, h->Th, m, mn, false, h->Cm, n, n * k, false, h->T[v], m, m * k);
+            put_u(h, e, h->Cm, n * k, n, 1, true);                     // T_u = Q^H
+            split_finish(h->ew, (int)m, (int)k, h->T[v], m * k, h->st, h->stream);
+        }
+    }
+    if (centre_up)
+        build_up(h, v);
+    else
+        build_down(h, v);
+}
+
+// Half-step of the two-site integrator below v (centre at v's parent on
+// entry and exit): every edge of the subtree and the edge above v is
+// updated forward once; v itself, between the updates of the edges that
+// meet there, is evolved backward (after each child edge).
+void visit2_fwd(ttn_handle* h, int v, double tau) {
+    const int u = h->parent[v], leg = leg_in_parent(h, v);
+    if (!is_bottom(h, v)) {
+        qr_toward(h, h->DL[u], h->DR[u], h->DP[u], h->T[u], leg, h->Rq);   // centre down to v
+        absorb(h, v, 2, h->Rq, false);
+        build_down(h, v);
+        visit2_fwd(h, h->ch0[v], tau);
+        evolve_node(h, v, -tau);
+        visit2_fwd(h, h->ch1[v], tau);
+        evolve_node(h, v, -tau);
+    }
+    update_edge2(h, v, tau, true);
+}
+
+// The exact reverse of visit2_fwd.
+void visit2_bwd(ttn_handle* h, int v, double tau) {
+    const int u = h->parent[v], leg = leg_in_parent(h, v);
+    if (is_bottom(h, v)) {
+        update_edge2(h, v, tau, true);
+        return;
+    }
+    update_edge2(h, v, tau, false);
+    evolve_node(h, v, -tau);
+    visit2_bwd(h, h->ch1[v], tau);
+    evolve_node(h, v, -tau);
+    visit2_bwd(h, h->ch0[v], tau);
+    qr_toward(h, h->DL[v], h->DR[v], h->DP[v], h->T[v], 2, h->Rq);         // centre back up to u
+    build_up(h, v);
+    absorb(h, u, leg, h->Rq, false);
+}
+
+void sweep2_fwd(ttn_handle* h, double tau) {
+    visit2_fwd(h, h->ch0[h->root], tau);
+    evolve_node(h, h->root, -tau);
+    visit2_fwd(h, h->ch1[h->root], tau);
+}
+
+void sweep2_bwd(ttn_handle* h, double tau) {
+    visit2_bwd(h, h->ch1[h->root], tau);
+    evolve_node(h, h->root, -tau);
+    visit2_bwd(h, h->ch0[h->root], tau);
+}
+
 void step_body(ttn_handle* h, double tau);
 
 void postorder(const ttn_handle* h, int v, std::vector<int>& out) {
@@ -1222,6 +1525,11 @@ void rebuild_up(ttn_handle* h) {
 
 void step_body(ttn_handle* h, double tau) {
     rebuild_up(h);
+    if (h->two_site) {
+        sweep2_fwd(h, tau);
+        sweep2_bwd(h, tau);
+        return;
+    }
     sweep_fwd(h, tau);
     sweep_bwd(h, tau);
 }
@@ -1564,6 +1872,13 @@ void validate(const ttn_config* c) {
     if (!(c->dress_eps >= 0) || !std::isfinite(c->c6) || !std::isfinite(c->leak_ratio) ||
         !(c->gamma >= 0) || !std::isfinite(c->gamma))
         throw StatusError{TTN_EINVAL, "bad scalar parameter"};
+    if (c->update != TTN_UPDATE_ONE_SITE && c->update != TTN_UPDATE_TWO_SITE)
+        throw StatusError{TTN_EINVAL, "unknown update"};
+    if (c->update == TTN_UPDATE_TWO_SITE) {
+        if (c->precision != TTN_PREC_FP64) throw StatusError{TTN_ENOTSUP, "the two-site update runs in FP64 only"};
+        if (c->gamma != 0.0) throw StatusError{TTN_ENOTSUP, "the two-site update needs a closed system"};
+        if (c->n_sites < 4) throw StatusError{TTN_ENOTSUP, "the two-site update needs at least four sites"};
+    }
     for (int i = 0; i < c->n_sites; ++i)
         for (int j = 0; j < i; ++j)
             if (c->pos_xy[2 * i] == c->pos_xy[2 * j] && c->pos_xy[2 * i + 1] == c->pos_xy[2 * j + 1])
@@ -1584,7 +1899,16 @@ void setup_config(ttn_handle* h, const ttn_config* c) {
     h->gamma = c->gamma;
     h->nonherm = c->gamma != 0.0;
     h->leaf_site.assign(c->leaf_order, c->leaf_order + c->n_sites);
+    h->two_site = c->update == TTN_UPDATE_TWO_SITE;
     build_tree(h);
+    if (h->two_site)
+        for (int v = 0; v < h->n_nodes; ++v) {
+            if (v == h->root) continue;
+            const Edge2 e = edge2(h, v);
+            if (std::min(e.m, e.n) > JAC_NMAX)
+                throw StatusError{TTN_ENOTSUP, "two-site split wider than the eigensolver (smaller side of a merged "
+                                               "tensor above 256)"};
+        }
 }
 
 // van der Waals couplings V_ij = C6 / d_ij^6 (Eq. c6, positive, i != j, cutoff)
@@ -1857,6 +2181,7 @@ int ttn_tdvp_step(ttn_handle* h, double dt, int32_t n_steps, ttn_step_stats* sta
                 ttn_step_stats& o = stats[i];
                 observables(h, &o.norm2, &o.energy);
                 std::memcpy(&o.min_r_diag, &s.min_rdiag_bits, sizeof(double));
+                std::memcpy(&o.max_discarded, &s.max_disc_bits, sizeof(double));
                 o.min_krylov = s.min_krylov;
                 o.reserved = 0;
                 // closed system: the norm is conserved; open system: it may only decay
@@ -2130,6 +2455,32 @@ int ttn_leg_contract_noalloc(int32_t precision, int32_t leg, int32_t DL, int32_t
     }
 }
 
+int ttn_herm_eig(int32_t n, void* d_a, void* d_v, void* d_w, void* d_order, void* hip_stream) {
+    StepDev* st = nullptr;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    try {
+        if (n < 1 || n > JAC_NMAX || !d_a || !d_v || !d_w || !d_order)
+            throw StatusError{TTN_EINVAL, "bad size or pointer"};
+        HIPCHECK(hipMalloc(&st, sizeof(StepDev)));
+        HIPCHECK(hipMemsetAsync(st, 0, sizeof(StepDev), s));
+        herm_eig((double*)d_a, n, (double*)d_v, (double*)d_w, (int*)d_order, st, s);
+        StepDev hs;
+        HIPCHECK(hipMemcpyAsync(&hs, st, sizeof(StepDev), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        HIPCHECK(hipFree(st));
+        st = nullptr;
+        if (hs.bad) throw StatusError{TTN_ENUMERIC, "Jacobi iteration did not converge"};
+        return TTN_OK;
+    } catch (const StatusError& e) {
+        if (st) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(st);
+        }
+        g_init_error = e.msg;
+        return e.code;
+    }
+}
+
 int ttn_profile_begin(ttn_handle* h) {
     if (!h) return TTN_EINVAL;
     if (h->poisoned) return TTN_ESTATE;
@@ -2207,7 +2558,7 @@ int ttn_validate_plan(const ttn_config* cfg, int32_t n_steps, char* msg, int32_t
         const int N = h->N, d = h->d;
         // record the steps for the adjoint, then walk the backward pass too
         // (closed systems only: the adjoint rejects an open system)
-        const bool adj = !h->nonherm;
+        const bool adj = !h->nonherm && !h->two_site;
         const int32_t k = std::max(1, n_steps / 2);
         {   // single-qubit channels on every site
             std::vector<double> ones((size_t)N * h->n_seg, 1.0);
@@ -2325,6 +2676,7 @@ int ttn_record_begin(ttn_handle* h, int32_t n_steps, int32_t ckpt_every, void* d
     try {
         if (!h->d_omega && !h->dry) throw StatusError{TTN_ESTATE, "ttn_set_pulses must be called first"};
         if (h->nonherm) throw StatusError{TTN_EINVAL, "the adjoint needs a Hermitian Hamiltonian (gamma = 0)"};
+        if (h->two_site) throw StatusError{TTN_ENOTSUP, "the adjoint covers the single-site update only"};
         record_begin(h, n_steps, ckpt_every, d_buf, bytes);
         if (!h->dry) HIPCHECK(hipGetLastError());
         return TTN_OK;

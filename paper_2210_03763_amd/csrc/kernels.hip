@@ -33,6 +33,17 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;   // valid in thread 0
 }
 
+// block_sum with the total returned in every thread (sh: blockDim / 64 + 1
+// doubles).
+__device__ inline double block_sum_all(double v, double* sh) {
+    const double r = block_sum(v, sh);
+    if (threadIdx.x == 0) sh[blockDim.x / 64] = r;
+    __syncthreads();
+    const double t = sh[blockDim.x / 64];
+    __syncthreads();
+    return t;
+}
+
 // Sums P values (P a power of two, 2 <= P <= 32) over the block with one
 // barrier: a butterfly inside each wave leaves value (l >> 1) & (P - 1),
 // summed over the wave, in lane l; the waves' results meet in sh (P per wave,
@@ -1740,6 +1751,258 @@ __global__ __launch_bounds__(64) void k_rdiag_min(const double* R, int D, StepDe
 void rdiag_min(const double* R, int D, StepDev* st, hipStream_t s) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_rdiag_min, dim3(1), dim3(64), 0, s, R, D, st);
+}
+
+// ---------------------------------------------------------------------------
+// Hermitian eigendecomposition (cyclic Jacobi) for the two-site split
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int JAC_THREADS = 1024;
+
+// Eigenvalues and eigenvectors of a Hermitian n x n matrix A (planar complex,
+// column-major; overwritten) by the cyclic Jacobi method with the round-robin
+// ordering: each of the n' - 1 rounds of a sweep (n' = n rounded up to even,
+// the extra index a zero row and column) rotates n' / 2 disjoint index pairs
+// at once, all rotations taken from the matrix before the round.  Pair
+// (p, q), b = A[p, q] = |b| e^{i phi}: J = diag(1, e^{-i phi}) R with the real
+// Jacobi rotation R = [[c, s], [-s, c]] that diagonalises
+// [[A_pp, |b|], [|b|, A_qq]] (t = sgn(tau) / (|tau| + sqrt(1 + tau^2)),
+// tau = (A_qq - A_pp) / (2 |b|), c = 1 / sqrt(1 + t^2), s = t c), applied as
+// A <- J^H A J and V <- V J.  A pair is skipped when
+// |b| <= tol sqrt(|A_pp A_qq|) (relative accuracy for positive definite
+// matrices) or |b| <= 4 eps sum_i |A_ii| (the rounding level of the matrix,
+// which pairs of numerically zero eigenvalues cannot get below); the
+// iteration stops after a sweep without a rotation, or after max_sweeps
+// (then st->bad is set).  Outputs: w[k] the k-th largest
+// eigenvalue, order[k] its column in V.
+__global__ __launch_bounds__(JAC_THREADS) void k_herm_jacobi(double* A, int n, double* V, double* w, int* order,
+                                                             int max_sweeps, double tol, StepDev* st) {
+    __shared__ double rc[JAC_NMAX / 2], rs[JAC_NMAX / 2], rer[JAC_NMAX / 2], rei[JAC_NMAX / 2];
+    __shared__ int rp[JAC_NMAX / 2], rq[JAC_NMAX / 2];
+    __shared__ int s_rot, s_done;
+    __shared__ double sh[32];
+    const int tid = threadIdx.x;
+    const int np = n + (n & 1), half = np / 2;
+    const int64_t nn = (int64_t)n * n;
+    double* Ai = A + nn;
+    double* Vi = V + nn;
+    double tr = 0.0;
+    for (int64_t e = tid; e < nn; e += JAC_THREADS) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        V[e] = i == j ? 1.0 : 0.0;
+        Vi[e] = 0.0;
+        if (i == j) tr += fabs(A[e]);
+    }
+    // off-diagonal entries at the rounding level of the whole matrix cannot
+    // be reduced further: a pair is also left alone below 4 eps sum |A_ii|
+    const double abs_floor = 4.0 * 2.220446049250313e-16 * block_sum_all(tr, sh);
+    if (tid == 0) s_done = 0;
+    __syncthreads();
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int r = 0; r < np - 1; ++r) {
+            if (tid < half) {
+                // circle method: slot 0 holds index 0, slots 1.. rotate
+                auto player = [&](int slot) { return slot == 0 ? 0 : 1 + (slot - 1 + r) % (np - 1); };
+                int p = player(tid), q = player(np - 1 - tid);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
+                if (q < n) {
+                    const double a = A[p + (int64_t)n * p], d = A[q + (int64_t)n * q];
+                    const double br = A[p + (int64_t)n * q], bi = Ai[p + (int64_t)n * q];
+                    const double ab = sqrt(br * br + bi * bi);
+                    if (ab > abs_floor && ab > tol * sqrt(fabs(a * d))) {
+                        const double tau = (d - a) / (2.0 * ab);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
+                        er = br / ab;   // e^{-i phi} = conj(b) / |b|
+                        ei = -bi / ab;
+                        s_rot = 1;
+                    }
+                }
+                rc[tid] = c;
+                rs[tid] = sn;
+                rer[tid] = er;
+                rei[tid] = ei;
+                rp[tid] = p;
+                rq[tid] = q;
+            }
+            __syncthreads();
+            // A <- J^H A J, one 2 x 2 block (pair P rows, pair Q columns) per item
+            for (int e = tid; e < half * half; e += JAC_THREADS) {
+                const int P = e % half, Q = e / half;
+                const int p0 = rp[P], q0 = rq[P], p1 = rp[Q], q1 = rq[Q];
+                const bool rowq = q0 < n, colq = q1 < n;
+                // block entries x[row][col], rows (p0, q0), columns (p1, q1)
+                double xr[2][2], xi[2][2];
+                const int rows[2] = {p0, q0}, cols[2] = {p1, q1};
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const bool ok = (a == 0 || rowq) && (b == 0 || colq);
+                        const int64_t o = rows[a] + (int64_t)n * cols[b];
+                        xr[a][b] = ok ? A[o] : 0.0;
+                        xi[a][b] = ok ? Ai[o] : 0.0;
+                    }
+                // rows: r_p = c x_p - s conj(e) x_q,  r_q = s x_p + c conj(e) x_q
+                {
+                    const double c = rc[P], sn = rs[P], er = rer[P], ei = -rei[P];   // conj(e)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const double qr = er * xr[1][b] - ei * xi[1][b], qi = er * xi[1][b] + ei * xr[1][b];
+                        const double pr = xr[0][b], pi = xi[0][b];
+                        xr[0][b] = c * pr - sn * qr;
+                        xi[0][b] = c * pi - sn * qi;
+                        xr[1][b] = sn * pr + c * qr;
+                        xi[1][b] = sn * pi + c * qi;
+                    }
+                }
+                // columns: k_p = c x_p - s e x_q,  k_q = s x_p + c e x_q
+                {
+                    const double c = rc[Q], sn = rs[Q], er = rer[Q], ei = rei[Q];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const double qr = er * xr[a][1] - ei * xi[a][1], qi = er * xi[a][1] + ei * xr[a][1];
+                        const double pr = xr[a][0], pi = xi[a][0];
+                        xr[a][0] = c * pr - sn * qr;
+                        xi[a][0] = c * pi - sn * qi;
+                        xr[a][1] = sn * pr + c * qr;
+                        xi[a][1] = sn * pi + c * qi;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        if (!((a == 0 || rowq) && (b == 0 || colq))) continue;
+                        const int64_t o = rows[a] + (int64_t)n * cols[b];
+                        A[o] = xr[a][b];
+                        Ai[o] = xi[a][b];
+                    }
+            }
+            // V <- V J on the columns of every pair
+            for (int e = tid; e < n * half; e += JAC_THREADS) {
+                const int i = e % n, Q = e / n;
+                const int p1 = rp[Q], q1 = rq[Q];
+                if (q1 >= n) continue;
+                const double c = rc[Q], sn = rs[Q], er = rer[Q], ei = rei[Q];
+                const int64_t op = i + (int64_t)n * p1, oq = i + (int64_t)n * q1;
+                const double pr = V[op], pi = Vi[op], xr = V[oq], xi = Vi[oq];
+                const double qr = er * xr - ei * xi, qi = er * xi + ei * xr;
+                V[op] = c * pr - sn * qr;
+                Vi[op] = c * pi - sn * qi;
+                V[oq] = sn * pr + c * qr;
+                Vi[oq] = sn * pi + c * qi;
+            }
+            __syncthreads();
+        }
+        const int rotated = s_rot;
+        __syncthreads();   // every thread has read s_rot before it is reset
+        if (!rotated) {
+            if (tid == 0) s_done = 1;
+            break;
+        }
+    }
+    __syncthreads();
+    // order[k]: the column of the k-th largest eigenvalue (ties by index)
+    for (int i = tid; i < n; i += JAC_THREADS) {
+        const double wi = A[i + (int64_t)n * i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double wj = A[j + (int64_t)n * j];
+            rank += (wj > wi || (wj == wi && j < i)) ? 1 : 0;
+        }
+        order[rank] = i;
+        w[rank] = wi;
+    }
+    if (tid == 0 && !s_done) atomicExch(&st->bad, 1);
+}
+}  // namespace
+
+namespace {
+// dst[c dc + s ds + p dp] = src[c sc + s ss + p sp] (conjugated if conj), for
+// c < K, s < S, p < P; planar complex with the given plane distances.
+__global__ void k_copy3(const double* src, int64_t src_plane, int64_t sc, int64_t ss, int64_t sp, double* dst,
+                        int64_t dst_plane, int64_t dc, int64_t ds, int64_t dp, int K, int S, int P, int conj) {
+    const int64_t total = (int64_t)K * S * P;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % K);
+        const int64_t r = e / K;
+        const int sidx = (int)(r % S), pidx = (int)(r / S);
+        const int64_t i = c * sc + sidx * ss + pidx * sp, o = c * dc + sidx * ds + pidx * dp;
+        dst[o] = src[i];
+        dst[o + dst_plane] = conj ? -src[i + src_plane] : src[i + src_plane];
+    }
+}
+
+// out[:, c] = V[:, order[c]] for c < k (n x n planar V, n x k planar out)
+__global__ void k_gather_cols(const double* V, int n, const int* order, int k, double* out) {
+    const int64_t total = (int64_t)n * k, nn = (int64_t)n * n, nk = (int64_t)n * k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), c = (int)(e / n);
+        const int64_t src = i + (int64_t)n * order[c];
+        out[e] = V[src];
+        out[e + nk] = V[src + nn];
+    }
+}
+
+// The kept weight of a truncated split, from the descending eigenvalues w
+// of its Gram matrix: kept = w_0 + .. + w_{k-1}, total = the sum of all n.
+// Scales the centre tensor x (count complex entries) by sqrt(total / kept),
+// restoring the norm of the untruncated tensor, and folds the discarded
+// weight 1 - kept / total into the step's maximum.
+__global__ void k_split_finish(const double* w, int n, int k, double* x, int64_t count, StepDev* st) {
+    __shared__ double sh[8];
+    double kept = 0, total = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        total += w[i];
+        if (i < k) kept += w[i];
+    }
+    kept = block_sum_all(kept, sh);
+    total = block_sum_all(total, sh);
+    const double f = kept > 0.0 ? sqrt(total / kept) : 1.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+        x[e] *= f;
+        x[e + count] *= f;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double disc = total > 0.0 ? 1.0 - kept / total : 0.0;
+        if (disc < 0.0) disc = 0.0;
+        if (!(kept > 0.0) || !(disc == disc)) atomicExch(&st->bad, 1);
+        atomicMax(&st->max_disc_bits, (unsigned long long)__double_as_longlong(disc));
+    }
+}
+}  // namespace
+
+void copy3(const double* src, int64_t src_plane, int64_t sc, int64_t ss, int64_t sp, double* dst, int64_t dst_plane,
+           int64_t dc, int64_t ds, int64_t dp, int K, int S, int P, bool conj, hipStream_t s) {
+    if (g_dry_run) return;
+    const int64_t total = (int64_t)K * S * P;
+    hipLaunchKernelGGL(k_copy3, dim3(grid_for(total)), dim3(256), 0, s, src, src_plane, sc, ss, sp, dst, dst_plane, dc,
+                       ds, dp, K, S, P, conj ? 1 : 0);
+}
+
+void gather_cols(const double* V, int n, const int* order, int k, double* out, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_gather_cols, dim3(grid_for((int64_t)n * k)), dim3(256), 0, s, V, n, order, k, out);
+}
+
+void split_finish(const double* w, int n, int k, double* x, int64_t count, StepDev* st, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_split_finish, dim3(grid_for(count)), dim3(256), 0, s, w, n, k, x, count, st);
+}
+
+void herm_eig(double* A, int n, double* V, double* w, int* order, StepDev* st, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_herm_jacobi, dim3(1), dim3(JAC_THREADS), 0, s, A, n, V, w, order, 60, 1e-15, st);
 }
 
 // ---------------------------------------------------------------------------

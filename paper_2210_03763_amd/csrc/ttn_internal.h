@@ -90,6 +90,7 @@ struct StepDev {
     int bad;                 // non-zero after a failed Cholesky pivot / NaN
     int min_krylov;
     unsigned long long min_rdiag_bits;   // positive double as ordered bits
+    unsigned long long max_disc_bits;    // non-negative double as ordered bits
     double scratch[8];
 };
 
@@ -154,6 +155,21 @@ void fill_zero_d(double* y, int64_t count, hipStream_t s);
 void herm_f2d(const float* in, double* out, int D, int count, hipStream_t s, bool raw_first = false);
 // dst = sum_{k < count} src_k for planar D x D FP64 matrices stored one after another
 void sum_mats(const double* src, int D, int count, double* dst, hipStream_t s);
+
+// Eigenvalues (descending, w[k]) and eigenvectors (columns order[k] of V) of
+// a Hermitian n x n matrix A (planar, column-major; destroyed), n <= JAC_NMAX,
+// by cyclic Jacobi in one workgroup; st->bad when it does not converge.
+constexpr int JAC_NMAX = 256;
+void herm_eig(double* A, int n, double* V, double* w, int* order, StepDev* st, hipStream_t s);
+// dst[c dc + s ds + p dp] = (conj) src[c sc + s ss + p sp], c < K, s < S, p < P
+void copy3(const double* src, int64_t src_plane, int64_t sc, int64_t ss, int64_t sp, double* dst, int64_t dst_plane,
+           int64_t dc, int64_t ds, int64_t dp, int K, int S, int P, bool conj, hipStream_t s);
+// out[:, c] = V[:, order[c]], c < k
+void gather_cols(const double* V, int n, const int* order, int k, double* out, hipStream_t s);
+// scales the centre x (count complex) of a split by sqrt(total / kept) of the
+// descending Gram eigenvalues w (n of them, k kept); records the discarded
+// weight 1 - kept / total in st->max_disc_bits
+void split_finish(const double* w, int n, int k, double* x, int64_t count, StepDev* st, hipStream_t s);
 
 // min over k of Re R[k][k] into st->min_rdiag_bits (R: D x D planar)
 void rdiag_min(const double* R, int D, StepDev* st, hipStream_t s);

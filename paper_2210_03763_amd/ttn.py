@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libttn.so")
 
 TTN_OK, TTN_EINVAL, TTN_ENOMEM, TTN_EDEVICE, TTN_ENUMERIC, TTN_ESTATE, TTN_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+UPDATE_ONE_SITE, UPDATE_TWO_SITE = 0, 1
 
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "ESTATE", -6: "ENOTSUP"}
 
@@ -30,7 +31,7 @@ class TTNError(RuntimeError):
 
 class Config(C.Structure):
     _fields_ = [("n_sites", C.c_int32), ("d", C.c_int32), ("chi", C.c_int32),
-                ("krylov_dim", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("krylov_dim", C.c_int32), ("precision", C.c_int32), ("update", C.c_int32),
                 ("c6", C.c_double), ("r_cut", C.c_double), ("leak_ratio", C.c_double),
                 ("pos_xy", C.POINTER(C.c_double)), ("leaf_order", C.POINTER(C.c_int32)),
                 ("init_product", C.POINTER(C.c_double)), ("dress_eps", C.c_double),
@@ -40,7 +41,7 @@ class Config(C.Structure):
 
 class StepStats(C.Structure):
     _fields_ = [("norm2", C.c_double), ("energy", C.c_double), ("min_r_diag", C.c_double),
-                ("min_krylov", C.c_int32), ("reserved", C.c_int32)]
+                ("min_krylov", C.c_int32), ("reserved", C.c_int32), ("max_discarded", C.c_double)]
 
 
 class KernelProf(C.Structure):
@@ -138,6 +139,7 @@ def make_config(w, keep: list) -> Config:
     cfg.chi = w.chi
     cfg.krylov_dim = w.krylov_dim
     cfg.precision = w.precision
+    cfg.update = int(getattr(w, "update", 0))
     cfg.c6 = w.c6
     cfg.r_cut = w.r_cut
     cfg.leak_ratio = w.leak_ratio
@@ -217,7 +219,7 @@ class TTN:
         self._check(rc, self.h)
         if stats:
             return [dict(norm2=a.norm2, energy=a.energy, min_r_diag=a.min_r_diag,
-                         min_krylov=a.min_krylov) for a in arr[:n_steps]]
+                         min_krylov=a.min_krylov, max_discarded=a.max_discarded) for a in arr[:n_steps]]
         return None
 
     def fidelity(self, target_sites=None):

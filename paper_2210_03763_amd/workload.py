@@ -74,6 +74,7 @@ class Workload:
     # [N, S] on the same segments as omega/delta; None = zero
     omega_x: Optional[np.ndarray] = None
     omega_z: Optional[np.ndarray] = None
+    update: int = 0           # 0 single-site TDVP, 1 two-site (two-tensor) update
 
     @property
     def n_sites(self) -> int:

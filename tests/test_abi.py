@@ -100,6 +100,12 @@ def _validate(w, n_steps=1):
                                                                lattice="hex", gates="pulse")),
     ("8x8 d4 chi128 fp32 open", lambda: W.make_ghz_program(8, 8, 4, 128, 1, 0.005, seed=1, eps=0.0,
                                                           precision=1).copy(gamma=0.02)),
+    ("2x2 d3 chi9 two-site", lambda: W.make_random_drive(2, 2, 3, 9, 1, 0.01, 1, seed=1).copy(update=1)),
+    ("2x4 d3 chi81 two-site", lambda: W.make_random_drive(4, 2, 3, 81, 1, 0.01, 1, seed=1).copy(update=1)),
+    ("4x4 d3 chi16 two-site", lambda: W.make_random_drive(4, 4, 3, 16, 1, 0.01, 1, seed=1).copy(update=1)),
+    ("4x4 d4 chi16 two-site", lambda: W.make_random_drive(4, 4, 4, 16, 1, 0.01, 1, seed=1).copy(update=1)),
+    ("8x8 d3 chi12 two-site", lambda: W.make_ghz_program(8, 8, 3, 12, 1, 0.005, seed=1, eps=0.0).copy(update=1)),
+    ("8x8 d4 chi16 two-site", lambda: W.make_ghz_program(8, 8, 4, 16, 1, 0.005, seed=1, eps=0.0).copy(update=1)),
 ])
 def test_launch_plan_stays_in_bounds(case):
     """Every GEMM operand and vector launch of init + steps + observables stays
@@ -128,3 +134,24 @@ def test_adjoint_query_sizes():
     assert out[2].value - out[0].value == 2 * state
     assert L.ttn_adjoint_query(C.byref(cfg), 20, 0, C.byref(out[0])) == T.TTN_EINVAL
 
+
+
+@pytest.mark.parametrize("case,code", [
+    ("two-site mixed precision", T.TTN_ENOTSUP),
+    ("two-site open system", T.TTN_ENOTSUP),
+    ("two-site split above 256", T.TTN_ENOTSUP),
+    ("unknown update", T.TTN_EINVAL),
+])
+def test_two_site_limits(case, code):
+    w = W.make_random_drive(4, 4, 3, 16, 1, 0.01, 1, seed=1).copy(update=1)
+    if case == "two-site mixed precision":
+        w = w.copy(precision=T.PREC_FP32)
+    elif case == "two-site open system":
+        w = w.copy(gamma=0.1)
+    elif case == "two-site split above 256":
+        w = W.make_random_drive(8, 8, 3, 32, 1, 0.01, 1, seed=1).copy(update=1)   # 32^2 x 32^2 splits
+    else:
+        w = w.copy(update=2)
+    with pytest.raises(T.TTNError) as e:
+        T.workspace_bytes(w)
+    assert e.value.code == code, case
