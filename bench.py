@@ -363,6 +363,99 @@ def run_bf16(w, steps, warmup, graphs=True):
     return out
 
 
+def run_two_site(steps, chi=12):
+    """Two-site (two-tensor) TDVP, FP64, on the 8x8, d = 3 GHZ-preparation
+    program at bond dimension chi (12 is the paper's): one warm-up step (it
+    captures the step graph), `steps` timed steps, then one step in a
+    profiling window for the contraction launches (the two-site matvecs are
+    FP64) and the largest discarded weight of the timed steps."""
+    import torch
+    from paper_2210_03763_amd import ttn, workload as W
+    w = W.make_ghz_program(8, 8, 3, chi, 200, 0.005, 2210037632, eps=0.05,
+                           name=f"8x8 d3 chi{chi} GHZ program, two-site").copy(update=ttn.UPDATE_TWO_SITE)
+    g = ttn.TTN(w, device="cuda:0")
+    g.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = g.step(steps, stats=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    g.profile_begin()
+    g.step(1)
+    p = g.profile_end()
+    F, _ = g.fidelity()
+    g.close()
+    k = p.heff
+    ach = (k.flops / 1e12) / (k.ms / 1e3) if k.ms > 0 else 0.0
+    return {"workload": w.name, "steps": steps, "ms_per_step": round(ms, 2), "steps_per_s": round(1e3 / ms, 3),
+            "max_discarded_weight": max(s["max_discarded"] for s in stats), "fidelity": F,
+            "matvec_launches": int(k.launches), "matvec_tflops_fp64": round(ach, 3),
+            "matvec_frac_of_fp64_peak": round(ach / PEAK_TFLOPS["fp64"], 4),
+            "matvec_ms_per_step": round(k.ms, 2), "note": "ms_per_step includes the statistics read-back per step"}
+
+
+def run_c4_gradient(n_params=16, h=1e-6, seed=2210037634, part=(0, 1)):
+    """The 8x8, d = 3, chi = 64 gradient workload at its stated size: 200
+    recorded steps with a checkpoint every 10, the gradient of the all-atom
+    GHZ fidelity with respect to the 64 x 8 x {Omega, Delta} pulse table by
+    the adjoint (FP64), and central differences of the device forward map at
+    n_params parameters drawn with numpy PCG64(seed) (step h)."""
+    import numpy as np
+    import torch
+    from paper_2210_03763_amd import ttn, workload as W
+    w = W.config("c4")
+    n = w.n_steps
+    os.environ["TTN_PROGRESS"] = "1"      # the backward pass reports its checkpoint blocks
+    g = ttn.TTN(w, device="cuda:0")
+    nbytes = g.record(n, w.ckpt_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for done in range(0, n, 20):
+        g.step(min(20, n - done))
+        print(f"[bench] c4 recorded steps: {min(n, done + 20)} of {n}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    F, _ = g.fidelity()
+    print(f"[bench] c4 forward: {t1 - t0:.1f} s", file=sys.stderr, flush=True)
+    go, gd = g.backward()
+    del os.environ["TTN_PROGRESS"]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    grad = np.concatenate([go.ravel(), gd.ravel()])
+    scale = float(np.abs(grad).max())
+    rng = np.random.Generator(np.random.PCG64(seed))
+    picks = sorted(rng.choice(grad.size, size=n_params, replace=False).tolist())
+    picks = picks[part[0]::part[1]]     # this call's share of the sampled parameters
+    rows = []
+    t3 = time.perf_counter()
+    for idx in picks:
+        arr = w.omega if idx < go.size else w.delta
+        i, sg = divmod(idx % go.size, go.shape[1])
+        base = arr[i, sg]
+        Fs = []
+        for x in (base + h, base - h):
+            arr[i, sg] = x
+            gg = ttn.TTN(w, device="cuda:0")
+            gg.step(n)
+            Fs.append(gg.fidelity()[0])
+            gg.close()
+        arr[i, sg] = base
+        fd = (Fs[0] - Fs[1]) / (2 * h)
+        rows.append({"param": ("omega" if idx < go.size else "delta") + f"[{i},{sg}]", "adjoint": float(grad[idx]),
+                     "central_difference": fd})
+        print(f"[bench] c4 {rows[-1]} ({time.perf_counter() - t3:.0f} s)", file=sys.stderr, flush=True)
+    t4 = time.perf_counter()
+    diffs = [abs(r["adjoint"] - r["central_difference"]) for r in rows]
+    return {"workload": w.name, "recorded_steps": n, "ckpt_every": w.ckpt_every, "F": F, "max_abs_grad": scale,
+            "fd_step": h, "fd_params": rows, "max_abs_diff": max(diffs),
+            "max_rel_diff_to_max_grad": max(diffs) / scale if scale > 0 else None,
+            "fwd_s": round(t1 - t0, 2), "bwd_s": round(t2 - t1, 2), "fd_s": round(t4 - t3, 1),
+            "adjoint_buffer_gib": round(nbytes / 2 ** 30, 2)}
+
+
 def run_open(w, steps, warmup, gamma):
     """Open-system mode (Eq. (eq:hoqs): -i gamma |r><r| per site, Arnoldi
     local exponentials) on the same workload: timed steps from the step
@@ -723,6 +816,13 @@ def main():
                     help="write the profiling window's contraction launch records (JSON) here")
     ap.add_argument("--bf16-steps", type=int, default=2,
                     help="also time the BF16x3 precision mode over this many steps")
+    ap.add_argument("--c4-fd", type=int, default=0,
+                    help="also run the 8x8 d=3 chi=64 gradient at its stated size (200 recorded steps, checkpoint "
+                         "every 10) against central differences at this many parameters (0: skip)")
+    ap.add_argument("--c4-fd-part", default="0/1", metavar="I/K",
+                    help="central differences only at every K-th sampled parameter starting at I")
+    ap.add_argument("--two-site-steps", type=int, default=2,
+                    help="also time the two-site update on the 8x8 d=3 GHZ program at chi 12 and 16 (0: skip)")
     ap.add_argument("--c5-steps", type=int, default=0,
                     help="also measure the 8x8 d=4 chi=256 repetition-code program over this many steps")
     ap.add_argument("--contract-stage", choices=["A", "B", "C", "D"], default=None,
@@ -850,6 +950,14 @@ def main():
     if args.c5_steps > 0:
         print(f"[bench] chi=256 repetition code: {args.c5_steps} steps", file=sys.stderr, flush=True)
         out["chi256_repetition_code"] = run_c5(args.c5_steps)
+    if args.c4_fd > 0:
+        print(f"[bench] 8x8 chi=64 gradient, 200 recorded steps, {args.c4_fd} central differences",
+              file=sys.stderr, flush=True)
+        part = tuple(int(x) for x in args.c4_fd_part.split("/"))
+        out["c4_gradient"] = run_c4_gradient(args.c4_fd, part=part)
+    if args.two_site_steps > 0:
+        print(f"[bench] two-site update: {args.two_site_steps} steps", file=sys.stderr, flush=True)
+        out["two_site"] = [run_two_site(args.two_site_steps, chi) for chi in (12, 16)]
     if args.sample_shots > 0:
         print(f"[bench] sampling: {args.sample_shots} shots", file=sys.stderr, flush=True)
         out["sampling"] = run_sampling(w, args.sample_shots)

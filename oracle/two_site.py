@@ -4,8 +4,8 @@ tensors (arXiv 2210.03763, Sec. "Tensor network simulations": the tree
 network is evolved by TDVP with a two-tensor update, the bond dimension chi
 being the convergence knob).
 
-TEST INFRASTRUCTURE.  Only tests/ may import this module; there is no device
-path for it.  It reuses the single-site oracle's tree, environments and
+TEST INFRASTRUCTURE.  Only tests/ may import this module; the device's
+two-site update (ttn_config.update) is checked against it.  It reuses the single-site oracle's tree, environments and
 Lanczos exponential (the same test-only package) and adds the two-site
 effective Hamiltonian, the SVD split and the two-site sweep.
 
