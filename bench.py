@@ -294,7 +294,7 @@ def run_c5(steps):
     w = W.config("c5")
     out = {"workload": w.name, "steps": steps}
     fw = {}
-    for prec, key in ((ttn.PREC_FP32, "mixed"), (ttn.PREC_FP64, "fp64")):
+    for prec, key in ((ttn.PREC_FP32, "mixed"), (ttn.PREC_FP64, "fp64"), (ttn.PREC_BF16X3, "bf16x3")):
         g = ttn.TTN(w.copy(precision=prec), device="cuda:0")
         g.step(1)
         torch.cuda.synchronize()
@@ -311,12 +311,16 @@ def run_c5(steps):
     out["abs_dF"] = abs(out["mixed_F"] - out["fp64_F"])
     out["state_infidelity_C"] = 1 - abs(ov) ** 2
     out["mixed_speedup"] = round(out["fp64_ms_per_step"] / out["mixed_ms_per_step"], 3)
+    ovb = fw["bf16x3"].overlap(fw["fp64"])
+    out["bf16x3_abs_dF"] = abs(out["bf16x3_F"] - out["fp64_F"])
+    out["bf16x3_state_infidelity_C"] = 1 - abs(ovb) ** 2
+    out["bf16x3_speedup"] = round(out["fp64_ms_per_step"] / out["bf16x3_ms_per_step"], 3)
     for g in fw.values():
         g.close()
     del fw
     torch.cuda.empty_cache()
     grads = {}
-    for prec, key in ((ttn.PREC_FP32, "mixed"), (ttn.PREC_FP64, "fp64")):
+    for prec, key in ((ttn.PREC_FP32, "mixed"), (ttn.PREC_FP64, "fp64"), (ttn.PREC_BF16X3, "bf16x3")):
         g = ttn.TTN(w.copy(precision=prec), device="cuda:0")
         g.step(1)
         nbytes = g.record(steps, 2)
@@ -337,10 +341,11 @@ def run_c5(steps):
         del g
         torch.cuda.empty_cache()
     scale = max(np.abs(grads["fp64"][0]).max(), np.abs(grads["fp64"][1]).max())
-    err = max(np.abs(grads["mixed"][0] - grads["fp64"][0]).max(), np.abs(grads["mixed"][1] - grads["fp64"][1]).max())
     out["max_abs_grad_fp64"] = scale
-    out["max_abs_grad_diff"] = err
-    out["mixed_speedup_fwd_adj"] = round(out["fp64_fwd_adj_ms_per_step"] / out["mixed_fwd_adj_ms_per_step"], 3)
+    for key in ("mixed", "bf16x3"):
+        err = max(np.abs(grads[key][0] - grads["fp64"][0]).max(), np.abs(grads[key][1] - grads["fp64"][1]).max())
+        out[f"{key}_max_abs_grad_diff"] = err
+        out[f"{key}_speedup_fwd_adj"] = round(out["fp64_fwd_adj_ms_per_step"] / out[f"{key}_fwd_adj_ms_per_step"], 3)
     return out
 
 

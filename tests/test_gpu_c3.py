@@ -1,5 +1,6 @@
 """The 8x8, d = 4, chi = 128 GHZ-program workload (the bench workload)
-against the oracle and across precisions.
+against the oracle and across precisions, and the 8x8, d = 3, chi = 64
+program over its full 200 steps against the oracle.
 
 * FP64 path after two steps against the oracle's stored run
   (tests/golden/c3_oracle_2steps.npz, written by tests/golden/make_golden.py,
@@ -118,6 +119,44 @@ def test_c3_gradient_mixed_and_bf16x3_vs_fp64():
     assert scale > 0
     assert out["mixed"] <= 1e-5 * scale, (out, scale)
     assert out["bf16x3"] <= 1e-4 * scale, (out, scale)
+
+
+def test_c2_200_steps_fp64_vs_oracle():
+    """The 8x8, d = 3, chi = 64 GHZ program over its full 200 steps against
+    the stored oracle run (tests/golden/c2_oracle_200steps.npz): fidelity,
+    norm^2 and relative energy of the last step within 1e-10, the smallest
+    R_kk of every step within 1e-6 relative, and 256 seeded entries of every
+    node tensor and the whole root tensor within 1e-9 (the error of two
+    trajectories grows slowly over the 200 steps; the achieved value is
+    printed)."""
+    z = np.load(os.path.join(os.path.dirname(GOLD), "c2_oracle_200steps.npz"))
+    w = W.config("c2")
+    assert str(z["workload"]) == w.name and int(z["steps"]) == 200
+    _say("[c2] fp64 200 steps")
+    g = T.TTN(w)
+    stats = []
+    for _ in range(10):
+        stats += g.step(20, stats=True)
+        _say(f"[c2] {len(stats)} steps")
+    F, _ = g.fidelity()
+    flat = g.export_state()
+    g.close()
+    shapes = W.node_shapes(64, 3, 64)
+    off = np.concatenate([[0], np.cumsum([a * b * c for a, b, c in shapes])])
+    err = 0.0
+    for v in range(len(shapes)):
+        err = max(err, float(np.abs(flat[off[v] + z[f"idx_{v}"]] - z[f"val_{v}"]).max()))
+    root = int(z["root_index"])
+    err_root = float(np.abs(flat[off[root]:off[root + 1]] - z["root"]).max())
+    dE = abs(stats[-1]["energy"] - float(z["energy"][-1])) / max(1.0, abs(float(z["energy"][-1])))
+    dN = abs(stats[-1]["norm2"] - float(z["norm2"][-1]))
+    rrel = float(np.abs(np.array([s["min_r_diag"] for s in stats]) / z["min_r_diag"] - 1).max())
+    res = dict(entry_err=err, root_err=err_root, dF=abs(F - float(z["F"])), dN=dN, dE=dE, min_r_rel=rrel,
+               F=float(z["F"]))
+    _say(f"[c2] fp64 vs oracle after 200 steps {res}")
+    assert res["dF"] <= 1e-10 and dN <= 1e-10 and dE <= 1e-10, res
+    assert rrel <= 1e-6, res
+    assert err <= 1e-9 and err_root <= 1e-9, res
 
 
 def teardown_module(module):
