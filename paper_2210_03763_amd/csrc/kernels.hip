@@ -190,6 +190,50 @@ __global__ __launch_bounds__(256) void k_scale_next(const double* x, int64_t n, 
 // block); with wf != nullptr w is first widened from the FP32 matvec output
 // wf (and stored).  KC is a template argument so that the per-thread arrays
 // hold exactly the vectors in use.
+template <int KC, int W>
+__device__ inline void multidot_body(const double* V, const double* w, int64_t n, const float* wf, double (&re)[KC],
+                                     double (&im)[KC]) {
+    // W consecutive elements per thread and step (16-byte loads for W = 2)
+    typedef double dv __attribute__((ext_vector_type(W)));
+    typedef float fv __attribute__((ext_vector_type(W)));
+    const int64_t nw = n / W;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nw; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q * W;
+        dv vr[KC], vi[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            vr[k] = *(const dv*)(V + 2 * n * k + i);
+            vi[k] = *(const dv*)(V + 2 * n * k + n + i);
+        }
+        dv wr, wi;
+        if (wf) {
+            const fv a = *(const fv*)(wf + i), b = *(const fv*)(wf + i + n);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                wr[e] = (double)a[e];
+                wi[e] = (double)b[e];
+            }
+            *(dv*)(const_cast<double*>(w) + i) = wr;
+            *(dv*)(const_cast<double*>(w) + i + n) = wi;
+        } else {
+            wr = *(const dv*)(w + i);
+            wi = *(const dv*)(w + i + n);
+        }
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                re[k] += vr[k][e] * wr[e] + vi[k][e] * wi[e];
+                im[k] += vr[k][e] * wi[e] - vi[k][e] * wr[e];
+            }
+    }
+}
+
+// partial[blk][k] = sum_i conj(V_k[i]) w[i] for k < KC (2 KC reals per
+// block); with wf != nullptr w is first widened from the FP32 matvec output
+// wf (and stored).  KC is a template argument so that the per-thread arrays
+// hold exactly the vectors in use; vectors of even length are read two
+// elements at a time.
 template <int KC>
 __global__ __launch_bounds__(256) void k_multidot_partial(const double* V, const double* w, int64_t n,
                                                          double* partial, const LanczosDev* lz, const float* wf) {
@@ -199,30 +243,10 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* V, const
     double re[KC], im[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) re[k] = im[k] = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double vr[KC], vi[KC];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            vr[k] = V[2 * n * k + i];
-            vi[k] = V[2 * n * k + n + i];
-        }
-        double wr, wi;
-        if (wf) {
-            wr = (double)wf[i];
-            wi = (double)wf[i + n];
-            const_cast<double*>(w)[i] = wr;
-            const_cast<double*>(w)[i + n] = wi;
-        } else {
-            wr = w[i];
-            wi = w[i + n];
-        }
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            re[k] += vr[k] * wr + vi[k] * wi;
-            im[k] += vr[k] * wi - vi[k] * wr;
-        }
-    }
+    if (n % 2 == 0 && (((uintptr_t)V | (uintptr_t)w | (uintptr_t)wf) & 15) == 0)
+        multidot_body<KC, 2>(V, w, n, wf, re, im);
+    else
+        multidot_body<KC, 1>(V, w, n, wf, re, im);
     double a[P];
 #pragma unroll
     for (int k = 0; k < P / 2; ++k) {
@@ -325,6 +349,47 @@ __global__ __launch_bounds__(1024) void k_multidot_final(const double* partial, 
 // the previous pass's nbin block partials itself (the same sums in every
 // block) and block 0 records them in the state (alpha_index as in
 // lz_record_projection); pin must not alias partial.
+template <int MODE, int KC, int W>
+__device__ inline void sub_fused_body(const double* V, double* w, int64_t n, const double* c, double (&pr)[KC],
+                                      double (&pi)[KC], double& nrm) {
+    // W consecutive elements per thread and step (16-byte loads for W = 2)
+    typedef double dv __attribute__((ext_vector_type(W)));
+    const int64_t nw = n / W;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nw; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q * W;
+        dv vr[KC], vi[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            vr[k] = *(const dv*)(V + 2 * n * k + i);
+            vi[k] = *(const dv*)(V + 2 * n * k + n + i);
+        }
+        dv wr = *(const dv*)(w + i), wi = *(const dv*)(w + i + n);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const double cr = c[2 * k], ci = c[2 * k + 1];
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                wr[e] -= cr * vr[k][e] - ci * vi[k][e];
+                wi[e] -= cr * vi[k][e] + ci * vr[k][e];
+            }
+        }
+        *(dv*)(w + i) = wr;
+        *(dv*)(w + i + n) = wi;
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            if (MODE == 1) {
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    pr[k] += vr[k][e] * wr[e] + vi[k][e] * wi[e];
+                    pi[k] += vr[k][e] * wi[e] - vi[k][e] * wr[e];
+                }
+            } else if (MODE == 2) {
+                nrm += wr[e] * wr[e] + wi[e] * wi[e];
+            }
+        }
+    }
+}
+
 template <int MODE, int KC>
 __global__ __launch_bounds__(256) void k_sub_fused(const double* V, double* w, int64_t n, double* partial,
                                                    LanczosDev* lz, const double* pin, int nbin, int alpha_index) {
@@ -344,33 +409,10 @@ __global__ __launch_bounds__(256) void k_sub_fused(const double* V, double* w, i
     double pr[KC], pi[KC], nrm = 0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) pr[k] = pi[k] = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double vr[KC], vi[KC];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            vr[k] = V[2 * n * k + i];
-            vi[k] = V[2 * n * k + n + i];
-        }
-        double wr = w[i], wi = w[i + n];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            const double cr = c[2 * k], ci = c[2 * k + 1];
-            wr -= cr * vr[k] - ci * vi[k];
-            wi -= cr * vi[k] + ci * vr[k];
-        }
-        w[i] = wr;
-        w[i + n] = wi;
-        if (MODE == 1) {
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                pr[k] += vr[k] * wr + vi[k] * wi;
-                pi[k] += vr[k] * wi - vi[k] * wr;
-            }
-        } else if (MODE == 2) {
-            nrm += wr * wr + wi * wi;
-        }
-    }
+    if (n % 2 == 0 && (((uintptr_t)V | (uintptr_t)w) & 15) == 0)
+        sub_fused_body<MODE, KC, 2>(V, w, n, c, pr, pi, nrm);
+    else
+        sub_fused_body<MODE, KC, 1>(V, w, n, c, pr, pi, nrm);
     if (MODE == 1) {
         double a[P];
 #pragma unroll
@@ -833,6 +875,23 @@ __global__ void k_lz_combine(const double* V, int64_t n, double* out, const Lanc
     const int m = lz->m_eff;
     if (threadIdx.x < 2 * KRYLOV_MAX) y[threadIdx.x] = lz->y[threadIdx.x] * lz->beta0;
     __syncthreads();
+    if (n % 2 == 0 && (((uintptr_t)V | (uintptr_t)out) & 15) == 0) {   // two elements per step, 16-byte loads
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n / 2;
+             q += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t i = 2 * q;
+            d2 re = {0, 0}, im = {0, 0};
+            for (int k = 0; k < m; ++k) {
+                const double* v = V + 2 * n * k;
+                const d2 vr = *(const d2*)(v + i), vi = *(const d2*)(v + i + n);
+                re += y[2 * k] * vr - y[2 * k + 1] * vi;
+                im += y[2 * k] * vi + y[2 * k + 1] * vr;
+            }
+            *(d2*)(out + i) = re;
+            *(d2*)(out + i + n) = im;
+        }
+        return;
+    }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double re = 0, im = 0;
