@@ -23,7 +23,10 @@ namespace {
 
 constexpr double LANCZOS_TOL = 1e-12;     // beta_{j+1} <= tol (|alpha_j| + beta_j)
 constexpr double COMPLETION_TOL = 1e-8;   // Gram-Schmidt acceptance for initial isometries
-constexpr int RED_BLOCKS = 2048;
+// workgroups of the Lanczos reductions over long vectors (four per CU): on
+// 2^21-element vectors 1024 measured a little faster than 1536 or 2048 (the
+// single-workgroup final sums shrink), 4096 and 8192 slower
+constexpr int RED_BLOCKS = 1024;
 
 struct StatusError {
     int code;

@@ -547,95 +547,113 @@ __global__ __launch_bounds__(256) void k_lz_beta(const double* partial, int nb, 
 // y = exp(-i tau H) e_1 for the m_eff x m_eff projection H of the Krylov
 // basis: the Taylor series of exp(B/s), B = -i tau H, applied s times to the
 // vector, with s chosen so that ||B/s||_1 <= 1/4 (terms are summed until they
-// stop changing the result in double precision); one thread per row of H for
-// the products H term.  H is the real symmetric tridiagonal (alpha, beta) of
-// a Lanczos basis, or the complex upper Hessenberg matrix of an Arnoldi
-// basis (columns in hs, subdiagonal beta) when lz->nonherm.
-__device__ void lz_expm_hessenberg(LanczosDev* lz, double tau, StepDev* st) {
-    constexpr int KM = KRYLOV_MAX;
-    __shared__ double Hr[KM][KM + 1], Hi[KM][KM + 1];
-    __shared__ double tr[KM], ti[KM], wr[KM], wi[KM], vr[KM], vi[KM];
-    const int m = lz->m_eff, t = threadIdx.x;
-    const bool herm = !lz->nonherm;
-    for (int e = t; e < KM * KM; e += blockDim.x) {
-        const int row = e % KM, col = e / KM;
-        double a = 0.0, b = 0.0;
-        if (row < m && col < m) {
-            if (herm) {
-                if (row == col)
-                    a = lz->alpha[col];
-                else if (row == col + 1)
-                    a = lz->beta[col];
-                else if (col == row + 1)
-                    a = lz->beta[row];
-            } else if (row <= col) {
-                a = lz->hs[2 * (col * KM + row)];
-                b = lz->hs[2 * (col * KM + row) + 1];
-            } else if (row == col + 1) {
-                a = lz->beta[col];
-            }
-        }
-        Hr[row][col] = a;
-        Hi[row][col] = b;
+// stop changing the result in double precision).  H is the real symmetric
+// tridiagonal (alpha, beta) of a Lanczos basis, or the complex upper
+// Hessenberg matrix of an Arnoldi basis (columns in hs, subdiagonal beta)
+// when lz->nonherm.  The first wave does all of it, lane t holding row t of
+// H and element t of the vectors (products with H by lane shuffles, the
+// stopping test by a wave reduction); the other waves of the block only meet
+// it at the closing barrier.
+
+// entry (row, col) of the projection (re, im), zero outside m x m
+__device__ inline double2 lz_h_entry(const LanczosDev* lz, bool herm, int m, int row, int col) {
+    double a = 0.0, b = 0.0;
+    if (row < 0 || col < 0 || row >= m || col >= m) return make_double2(a, b);
+    if (herm) {
+        if (row == col)
+            a = lz->alpha[col];
+        else if (row == col + 1)
+            a = lz->beta[col];
+        else if (col == row + 1)
+            a = lz->beta[row];
+    } else if (row <= col) {
+        a = lz->hs[2 * (col * KRYLOV_MAX + row)];
+        b = lz->hs[2 * (col * KRYLOV_MAX + row) + 1];
+    } else if (row == col + 1) {
+        a = lz->beta[col];
     }
-    if (t < KM) {
-        vr[t] = t == 0 ? 1.0 : 0.0;
-        vi[t] = 0.0;
+    return make_double2(a, b);
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void lz_expm_hessenberg(LanczosDev* lz, double tau, StepDev* st) {
+    constexpr int KM = KRYLOV_MAX;
+    const int t = threadIdx.x;
+    if (t < 64) {
+        const int m = lz->m_eff;
+        const bool herm = !lz->nonherm;
+        // row t of H (Hessenberg case; the tridiagonal case reads its three
+        // entries below)
+        double hr[KM], hi[KM];
+#pragma unroll
+        for (int c = 0; c < KM; ++c) {
+            const double2 e = herm ? make_double2(0.0, 0.0) : lz_h_entry(lz, false, m, t, c);
+            hr[c] = e.x;
+            hi[c] = e.y;
+        }
+        // H[t][t-1], H[t][t], H[t][t+1] (tridiagonal)
+        const double dl = herm ? lz_h_entry(lz, true, m, t, t - 1).x : 0.0;
+        const double dd = herm ? lz_h_entry(lz, true, m, t, t).x : 0.0;
+        const double du = herm ? lz_h_entry(lz, true, m, t, t + 1).x : 0.0;
+        // 1-norm bound of tau H: the largest column sum (lane t sums column t
+        // in row order)
+        double cs = 0;
+        for (int row = 0; row < m; ++row) {
+            const double2 e = lz_h_entry(lz, herm, m, row, t);
+            cs += fabs(e.x) + fabs(e.y);
+        }
+        double nrm = wave_max(t < m ? cs : 0.0) * fabs(tau);
+        int ns = (int)ceil(nrm / 0.25);
+        if (ns < 1) ns = 1;
+        const double h = tau / ns;
+        double vr = t == 0 ? 1.0 : 0.0, vi = 0.0;
+        for (int rep = 0; rep < ns; ++rep) {
+            double tr = vr, ti = vi, wr = vr, wi = vi;
+            for (int k = 1; k <= 40; ++k) {
+                // term <- (-i h H term) / k
+                double sr = 0, si = 0;
+                if (herm) {
+                    const double trl = __shfl(tr, t > 0 ? t - 1 : 0, 64), til = __shfl(ti, t > 0 ? t - 1 : 0, 64);
+                    const double tru = __shfl(tr, t < 63 ? t + 1 : 63, 64), tiu = __shfl(ti, t < 63 ? t + 1 : 63, 64);
+                    sr = dl * trl + dd * tr + du * tru;
+                    si = dl * til + dd * ti + du * tiu;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < KM; ++c) {
+                        const double trc = __shfl(tr, c, 64), tic = __shfl(ti, c, 64);
+                        sr += hr[c] * trc - hi[c] * tic;
+                        si += hr[c] * tic + hi[c] * trc;
+                    }
+                }
+                const double f = h / k;
+                if (t < m) {
+                    tr = f * si;
+                    ti = -f * sr;
+                    wr += tr;
+                    wi += ti;
+                }
+                const double tmax = wave_max(t < m ? fabs(tr) + fabs(ti) : 0.0);
+                const double wmax = wave_max(t < m ? fabs(wr) + fabs(wi) : 0.0);
+                if (tmax <= 1e-18 * wmax) break;   // the same decision in every lane
+            }
+            vr = wr;
+            vi = wi;
+        }
+        if (t < KM) {
+            lz->y[2 * t] = t < m ? vr : 0.0;
+            lz->y[2 * t + 1] = t < m ? vi : 0.0;
+        }
+        if (t == 0) atomicMin(&st->min_krylov, m);
     }
     __syncthreads();
-    // 1-norm bound of tau H: the largest column sum
-    double nrm = 0;
-    for (int col = 0; col < m; ++col) {
-        double cs = 0;
-        for (int row = 0; row < m; ++row) cs += fabs(Hr[row][col]) + fabs(Hi[row][col]);
-        nrm = cs > nrm ? cs : nrm;
-    }
-    nrm *= fabs(tau);
-    int ns = (int)ceil(nrm / 0.25);
-    if (ns < 1) ns = 1;
-    const double h = tau / ns;
-    for (int rep = 0; rep < ns; ++rep) {
-        if (t < KM) {
-            tr[t] = wr[t] = vr[t];
-            ti[t] = wi[t] = vi[t];
-        }
-        __syncthreads();
-        for (int k = 1; k <= 40; ++k) {
-            // term <- (-i h H term) / k
-            double sr = 0, si = 0;
-            if (t < m)
-                for (int c = 0; c < m; ++c) {
-                    sr += Hr[t][c] * tr[c] - Hi[t][c] * ti[c];
-                    si += Hr[t][c] * ti[c] + Hi[t][c] * tr[c];
-                }
-            __syncthreads();
-            const double f = h / k;
-            if (t < m) {
-                tr[t] = f * si;
-                ti[t] = -f * sr;
-                wr[t] += tr[t];
-                wi[t] += ti[t];
-            }
-            __syncthreads();
-            double tmax = 0, wmax = 0;
-            for (int i = 0; i < m; ++i) {
-                const double ta = fabs(tr[i]) + fabs(ti[i]), wa = fabs(wr[i]) + fabs(wi[i]);
-                tmax = ta > tmax ? ta : tmax;
-                wmax = wa > wmax ? wa : wmax;
-            }
-            if (tmax <= 1e-18 * wmax) break;   // the same decision in every thread
-        }
-        if (t < KM) {
-            vr[t] = wr[t];
-            vi[t] = wi[t];
-        }
-        __syncthreads();
-    }
-    if (t < KM) {
-        lz->y[2 * t] = t < m ? vr[t] : 0.0;
-        lz->y[2 * t + 1] = t < m ? vi[t] : 0.0;
-    }
-    if (t == 0) atomicMin(&st->min_krylov, m);
 }
 
 __global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
@@ -654,42 +672,62 @@ __global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
 // ---------------------------------------------------------------------------
 constexpr int SMALL_THREADS = 256;
 
+// Elements owned by a thread of the fused kernel: i = threadIdx.x +
+// SMALL_THREADS t, t < SMALL_PER (n <= SMALL_EVOLVE_N), with their (l, r, p)
+// split computed once per launch.  Every element-wise pass of the kernel uses
+// this ownership, so the only barriers are those that publish a whole vector
+// (the matvec input and the left/right images) or a reduction.
+constexpr int SMALL_PER = (int)(SMALL_EVOLVE_N / SMALL_THREADS);
+static_assert(SMALL_PER * SMALL_THREADS == SMALL_EVOLVE_N, "elements must split evenly over the threads");
+struct SmallIdx {
+    int l[SMALL_PER], r[SMALL_PER], p[SMALL_PER];
+};
+
 // y = Op x; S holds the left (U_k = L_k x_L x, k = 1..sL) and right (Z_j =
-// R_j x_R x) images, slot stride 2n
+// R_j x_R x) images, slot stride 2n.  y is written only at the calling
+// thread's own elements (no closing barrier).
 __device__ void small_matvec(const double* L, const double* Rr, const double* B, const double* W, int DL, int DR,
-                             int DP, int sL, int sR, const double* x, double* S, double* y) {
+                             int DP, int sL, int sR, const SmallIdx& ix, const double* x, double* S, double* y) {
     const int n = DL * DR * DP;
     const int L2 = DL * DL, R2 = DR * DR, P2 = DP * DP;
     const int nz = (W && sR > 0) ? sR : 0;
-    for (int e = threadIdx.x; e < n * (sL + nz); e += blockDim.x) {
-        const int k = e / n, i = e % n;
-        const int l = i % DL, r = (i / DL) % DR, p = i / (DL * DR);
-        double ar = 0, ai = 0;
-        if (k < sL) {
-            const double* op = L + 2 * L2 * (k + 1);
+    for (int k = 0; k < sL + nz; ++k) {
+        const bool left = k < sL;
+        const double* op = left ? L + 2 * L2 * (k + 1) : Rr + 2 * R2 * (k - sL + 1);
+#pragma unroll
+        for (int t = 0; t < SMALL_PER; ++t) {
+            const int i = threadIdx.x + SMALL_THREADS * t;
+            if (i < n) {
+                const int l = ix.l[t], r = ix.r[t], p = ix.p[t];
+                double ar = 0, ai = 0;
+                if (left) {
 #pragma unroll 4
-            for (int q = 0; q < DL; ++q) {
-                const double orr = op[l + DL * q], oi = op[L2 + l + DL * q];
-                const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
-                ar += orr * xr - oi * xi;
-                ai += orr * xi + oi * xr;
-            }
-        } else {
-            const double* op = Rr + 2 * R2 * (k - sL + 1);
+                    for (int q = 0; q < DL; ++q) {
+                        const double orr = op[l + DL * q], oi = op[L2 + l + DL * q];
+                        const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
+                        ar += orr * xr - oi * xi;
+                        ai += orr * xi + oi * xr;
+                    }
+                } else {
 #pragma unroll 4
-            for (int q = 0; q < DR; ++q) {
-                const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
-                const double xr = x[l + DL * (q + DR * p)], xi = x[n + l + DL * (q + DR * p)];
-                ar += orr * xr - oi * xi;
-                ai += orr * xi + oi * xr;
+                    for (int q = 0; q < DR; ++q) {
+                        const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
+                        const double xr = x[l + DL * (q + DR * p)], xi = x[n + l + DL * (q + DR * p)];
+                        ar += orr * xr - oi * xi;
+                        ai += orr * xi + oi * xr;
+                    }
+                }
+                S[2 * n * k + i] = ar;
+                S[2 * n * k + n + i] = ai;
             }
         }
-        S[2 * n * k + i] = ar;
-        S[2 * n * k + n + i] = ai;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int l = i % DL, r = (i / DL) % DR, p = i / (DL * DR);
+#pragma unroll
+    for (int t = 0; t < SMALL_PER; ++t) {
+        const int i = threadIdx.x + SMALL_THREADS * t;
+        if (i >= n) continue;
+        const int l = ix.l[t], r = ix.r[t], p = ix.p[t];
         double ar = 0, ai = 0;
 #pragma unroll 4
         for (int q = 0; q < DL; ++q) {   // block Hamiltonian of the left leg
@@ -702,8 +740,8 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
             for (int k = 0; k <= sL; ++k) {   // right leg: H_R x + sum_i A_i U_i
                 const double* op = B + 2 * R2 * k;
                 const double* src = k == 0 ? x : S + 2 * n * (k - 1);
-    #pragma unroll 4
-            for (int q = 0; q < DR; ++q) {
+#pragma unroll 4
+                for (int q = 0; q < DR; ++q) {
                     const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
                     const double xr = src[l + DL * (q + DR * p)], xi = src[n + l + DL * (q + DR * p)];
                     ar += orr * xr - oi * xi;
@@ -725,28 +763,45 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
         y[i] = ar;
         y[n + i] = ai;
     }
-    __syncthreads();
 }
 
-// c_k = <v_k, w> for k < kc (planar vectors of n in LDS), into c[2 kc] (LDS)
-__device__ void small_project(const double* V, int kc, const double* w, int n, double* c, double* sh32) {
-    double a[32];
+// c_k = <v_k, w> for k < kc (planar vectors of n in LDS) over the calling
+// thread's own elements, summed over the block with P = the smallest power
+// of two >= 2 kc values; the totals land in c[2 kc] (LDS) behind one barrier.
+template <int P>
+__device__ void small_project_p(const double* V, int kc, const double* w, int n, double* c, double* sh) {
+    double a[P];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) a[k] = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int k = 0; k < P; ++k) a[k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < SMALL_PER; ++t) {
+        const int i = threadIdx.x + SMALL_THREADS * t;
+        if (i >= n) continue;
         const double wr = w[i], wi = w[n + i];
 #pragma unroll
-        for (int k = 0; k < KRYLOV_MAX; ++k)
+        for (int k = 0; k < P / 2; ++k)
             if (k < kc) {
                 const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
                 a[2 * k] += vr * wr + vi * wi;
                 a[2 * k + 1] += vr * wi - vi * wr;
             }
     }
-    const double t = block_sum32(a, sh32);
+    const double tot = block_sum_p<P>(a, sh);
+    if (threadIdx.x < 2 * kc) c[threadIdx.x] = tot;
     __syncthreads();
-    if (threadIdx.x < 2 * kc) c[threadIdx.x] = t;
-    __syncthreads();
+}
+
+__device__ void small_project(const double* V, int kc, const double* w, int n, double* c, double* sh) {
+    if (kc <= 1)
+        small_project_p<2>(V, kc, w, n, c, sh);
+    else if (kc <= 2)
+        small_project_p<4>(V, kc, w, n, c, sh);
+    else if (kc <= 4)
+        small_project_p<8>(V, kc, w, n, c, sh);
+    else if (kc <= 8)
+        small_project_p<16>(V, kc, w, n, c, sh);
+    else
+        small_project_p<32>(V, kc, w, n, c, sh);
 }
 
 __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL, const double* gR, const double* gB,
@@ -777,20 +832,29 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
         for (int e = threadIdx.x; e < 2 * R2 * (1 + sL); e += blockDim.x) B[e] = gB[e];
     if (gW)
         for (int e = threadIdx.x; e < 2 * P2 * (1 + sL + sR); e += blockDim.x) W[e] = gW[e];
-    // v_0 = x / ||x||
-    double a[32];
+    SmallIdx ix;
 #pragma unroll
-    for (int k = 0; k < 32; ++k) a[k] = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int t = 0; t < SMALL_PER; ++t) {
+        const int i = threadIdx.x + SMALL_THREADS * t;
+        ix.l[t] = i % DL;
+        ix.r[t] = (i / DL) % DR;
+        ix.p[t] = i / (DL * DR);
+    }
+    // v_0 = x / ||x||
+    double a[2] = {0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < SMALL_PER; ++t) {
+        const int i = threadIdx.x + SMALL_THREADS * t;
+        if (i >= n) continue;
         const double xr = x[i], xi = x[n + i];
         w[i] = xr;
         w[n + i] = xi;
         a[0] += xr * xr + xi * xi;
     }
-    double t = block_sum32(a, sh32);
+    double tot = block_sum_p<2>(a, sh32);
     if (threadIdx.x == 0) {
-        lz.beta0 = sqrt(t);
-        lz.zero = t == 0.0 ? 1 : 0;
+        lz.beta0 = sqrt(tot);
+        lz.zero = tot == 0.0 ? 1 : 0;
         lz.done = lz.zero;
         lz.m_eff = 0;
         lz.nonherm = nonherm;
@@ -804,8 +868,8 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
     __syncthreads();
     for (int j = 0; j < m; ++j) {
         const int kc = j + 1;
-        small_matvec(L, nz ? Rr : nullptr, gB ? B : nullptr, gW ? W : nullptr, DL, DR, DP, sL, sR, V + 2 * n * j, S,
-                     w);
+        small_matvec(L, nz ? Rr : nullptr, gB ? B : nullptr, gW ? W : nullptr, DL, DR, DP, sL, sR, ix,
+                     V + 2 * n * j, S, w);
         small_project(V, kc, w, n, c, sh32);
         if (threadIdx.x == 0) {
             lz.alpha[j] = c[2 * j];
@@ -813,9 +877,15 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
         }
         if (nonherm && threadIdx.x < 2 * kc) lz.hs[2 * j * KRYLOV_MAX + threadIdx.x] = c[threadIdx.x];
         if (j == m - 1) break;
-        // w -= V c, second projection, w -= V c'
+        // w -= V c, second projection, w -= V c' (each thread on its own
+        // elements: the projections' barriers order these passes)
+        a[0] = 0.0;
+        a[1] = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+#pragma unroll
+            for (int t = 0; t < SMALL_PER; ++t) {
+                const int i = threadIdx.x + SMALL_THREADS * t;
+                if (i >= n) continue;
                 double wr = w[i], wi = w[n + i];
                 for (int k = 0; k < kc; ++k) {
                     const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
@@ -824,19 +894,16 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
                 }
                 w[i] = wr;
                 w[n + i] = wi;
+                if (pass == 1) a[0] += wr * wr + wi * wi;
             }
-            __syncthreads();
             if (pass == 0) {
                 small_project(V, kc, w, n, c, sh32);
                 if (nonherm && threadIdx.x < 2 * kc) lz.hs[2 * j * KRYLOV_MAX + threadIdx.x] += c[threadIdx.x];
             }
         }
-#pragma unroll
-        for (int k = 0; k < 32; ++k) a[k] = 0.0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) a[0] += w[i] * w[i] + w[n + i] * w[n + i];
-        t = block_sum32(a, sh32);
+        tot = block_sum_p<2>(a, sh32);
         if (threadIdx.x == 0) {
-            const double b = sqrt(t);
+            const double b = sqrt(tot);
             const double bprev = j > 0 ? lz.beta[j - 1] : 0.0;
             const bool stop = !(b > tol * (fabs(lz.alpha[j]) + bprev));
             if (stop)
@@ -1597,7 +1664,8 @@ __device__ inline void cb_inv_diag(const double* lr_, const double* li_, const d
 }
 
 // G (D x D Hermitian, planar, column-major) = L L^H; Linv = L^{-1} (lower),
-// R = L^H (upper).  work: 2 Dp^2 doubles (Dp = 16 ceil(D / 16)).
+// R = L^H (upper).  work: 2 Dp^2 doubles (Dp = 16 ceil(D / 16)), untouched
+// when D is a multiple of 16.
 __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D, double* Linv, double* R,
                                                          double* work, StepDev* st) {
     __shared__ double s_re[CB_NBLK * 256], s_im[CB_NBLK * 256];
@@ -1607,22 +1675,49 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NB = (D + CB - 1) / CB, Dp = NB * CB;
     const int64_t DD = (int64_t)D * D, P2 = (int64_t)Dp * Dp;
-    double* Xr = work;   // padded inverse, Dp x Dp column-major
-    double* Xi = work + P2;
+    // the inverse is built in place in Linv when D is a whole number of
+    // blocks (no padding), else in the padded work array and copied out
+    const bool direct = Dp == D;
+    double* Xr = direct ? Linv : work;   // Dp x Dp column-major
+    double* Xi = direct ? Linv + DD : work + P2;
     double* dall = s_dinv;            // 1 / L_jj of every diagonal block, 16 per block
     double* csw = s_cs + 64 * wave;   // per-wave scratch (32 used)
     if (tid == 0) s_bad = 0;
     const int nbl = NB * (NB + 1) / 2;
-    for (int b = wave; b < nbl; b += CB_WAVES) {
-        int I = 0;
-        while ((I + 1) * (I + 2) / 2 <= b) ++I;
-        const int J = b - I * (I + 1) / 2;
-        for (int rc = lane; rc < 256; rc += 64) {
-            const int r = rc & 15, c = rc >> 4, gi = CB * I + r, gj = CB * J + c;
-            const bool in = gi < D && gj < D;
-            s_re[256 * b + rc] = in ? G[gi + (int64_t)D * gj] : (gi == gj ? 1.0 : 0.0);
-            s_im[256 * b + rc] = in ? G[DD + gi + (int64_t)D * gj] : 0.0;
+    {
+        // lower blocks of G into LDS (packed by cb_bidx): every load of a
+        // thread is issued before its first LDS store
+        constexpr int LQ = CB_NBLK * 256 / CB_THREADS;
+        static_assert(LQ * CB_THREADS == CB_NBLK * 256, "blocks must split evenly over the threads");
+        double gr[LQ], gim[LQ];
+#pragma unroll
+        for (int q = 0; q < LQ; ++q) {
+            const int e = tid + CB_THREADS * q, b = e >> 8, rc = e & 255;
+            int I = 0;
+            while ((I + 1) * (I + 2) / 2 <= b) ++I;
+            const int J = b - I * (I + 1) / 2;
+            const int gi = CB * I + (rc & 15), gj = CB * J + (rc >> 4);
+            const bool in = b < nbl && gi < D && gj < D;
+            gr[q] = in ? G[gi + (int64_t)D * gj] : (gi == gj ? 1.0 : 0.0);
+            gim[q] = in ? G[DD + gi + (int64_t)D * gj] : 0.0;
         }
+#pragma unroll
+        for (int q = 0; q < LQ; ++q) {
+            const int e = tid + CB_THREADS * q;
+            if ((e >> 8) < nbl) {
+                s_re[e] = gr[q];
+                s_im[e] = gim[q];
+            }
+        }
+        // blocks strictly above the diagonal of an in-place inverse are zero
+        if (direct)
+            for (int64_t e = tid; e < DD; e += CB_THREADS) {
+                const int i = (int)(e % D), j = (int)(e / D);
+                if ((i >> 4) < (j >> 4)) {
+                    Linv[e] = 0.0;
+                    Linv[DD + e] = 0.0;
+                }
+            }
     }
     __syncthreads();
     int bad = 0;
@@ -1764,13 +1859,14 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
         __threadfence_block();
         __syncthreads();
     }
-    for (int j = wave; j < D; j += CB_WAVES)
-        for (int i = lane; i < D; i += 64) {
-            const bool lo = i >= j;
-            const int64_t g = i + (int64_t)Dp * j;
-            Linv[i + (int64_t)D * j] = lo ? Xr[g] : 0.0;
-            Linv[DD + i + (int64_t)D * j] = lo ? Xi[g] : 0.0;
-        }
+    if (!direct)
+        for (int j = wave; j < D; j += CB_WAVES)
+            for (int i = lane; i < D; i += 64) {
+                const bool lo = i >= j;
+                const int64_t g = i + (int64_t)Dp * j;
+                Linv[i + (int64_t)D * j] = lo ? Xr[g] : 0.0;
+                Linv[DD + i + (int64_t)D * j] = lo ? Xi[g] : 0.0;
+            }
     __syncthreads();
     if (tid == 0 && s_bad) atomicExch(&st->bad, 1);
 }
