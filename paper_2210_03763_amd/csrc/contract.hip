@@ -779,28 +779,48 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
     const bool mfma_ok = K >= 16 && g.Kin % 16 == 0 && g.M >= 16 && g.N >= 16 && (g.sam == 1 || g.sak == 1) &&
                          (g.sbn == 1 || g.sbk == 1) && off32;
     if (mfma_ok) {
-        // tile choice: large tiles when the grid still fills the chip
-        const bool big = g.M >= 128 && g.N >= (sizeof(R) == 4 ? 128 : 64);
-        const int BM = big ? 128 : 64;
-        const int BN = big ? (sizeof(R) == 4 ? 128 : 64) : 64;
-        // FP32 large tiles take 32-wide k-tiles (half the barriers) where the
-        // inner contraction extent allows them
-        const int kq = (sizeof(R) == 4 && big && g.Kin % 32 == 0) ? 32 : 16;
+        // tile choice: the large tiles, unless their grid (after split-K) would
+        // leave more than half of the 256 CUs idle; then the small tiles, whose
+        // grid is four times larger and whose splits may be finer
+        struct Plan {
+            bool large;
+            int bm, bn, kq, tilesM, tilesN, splits;
+            int64_t tiles;
+        };
+        auto plan = [&](bool large) {
+            Plan p;
+            p.large = large;
+            p.bm = large ? 128 : 64;
+            p.bn = large ? (sizeof(R) == 4 ? 128 : 64) : 64;
+            // FP32 large tiles take 32-wide k-tiles (half the barriers) where
+            // the inner contraction extent allows them
+            p.kq = (sizeof(R) == 4 && large && g.Kin % 32 == 0) ? 32 : 16;
+            p.tilesM = (g.M + p.bm - 1) / p.bm;
+            p.tilesN = (g.N + p.bn - 1) / p.bn;
+            p.tiles = (int64_t)p.tilesM * p.tilesN * nbatch;
+            p.splits = 1;
+            const int ktiles = K / 16;
+            // split K until the grid covers the chip once: 256 workgroups of the
+            // large tiles (one resident per CU), 512 of the small ones (two per
+            // CU); a split keeps at least four 16-wide k-tiles (large) or two
+            const int64_t target = large ? 256 : 512;
+            const int minkt = large ? 4 : 2;
+            if (p.tiles < 256 && ktiles >= 2 * minkt && (int64_t)g.M * g.N < (1LL << 31)) {
+                p.splits = (int)std::min<int64_t>((target + p.tiles - 1) / p.tiles, ktiles / minkt);
+                const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
+                const int64_t cap = per > 0 ? ws.bytes / per : 1;
+                if (p.splits > cap) p.splits = (int)cap;
+                if (p.splits < 1) p.splits = 1;
+            }
+            return p;
+        };
+        Plan pl = plan(g.M >= 128 && g.N >= (sizeof(R) == 4 ? 128 : 64));
+        if (pl.large && pl.tiles * pl.splits < 128) pl = plan(false);
+        const bool big = pl.large;
+        const int BM = pl.bm, kq = pl.kq, tilesM = pl.tilesM, tilesN = pl.tilesN;
+        const int64_t tiles = pl.tiles;
+        int splits = pl.splits;
         const bool bf16 = sizeof(R) == 4 && g.split && big && kq == 32;
-        const int tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
-        const int64_t tiles = (int64_t)tilesM * tilesN * nbatch;
-        int splits = 1;
-        const int ktiles = K / 16;
-        // split K until the grid covers the chip once: 256 workgroups of the
-        // large tiles (one resident per CU), 512 of the small ones (two per CU)
-        const int64_t target = big ? 256 : 512;
-        if (tiles < 256 && ktiles >= 8 && (int64_t)g.M * g.N < (1LL << 31)) {
-            splits = (int)std::min<int64_t>((target + tiles - 1) / tiles, ktiles / 4);
-            const int64_t per = 2 * (int64_t)g.M * g.N * nbatch * (int64_t)sizeof(R);
-            const int64_t cap = per > 0 ? ws.bytes / per : 1;
-            if (splits > cap) splits = (int)cap;
-            if (splits < 1) splits = 1;
-        }
         int kchunk = K;
         if (splits > 1) {
             kchunk = ((K / kq + splits - 1) / splits) * kq;

@@ -1550,21 +1550,30 @@ __device__ inline cb_d4 cb_mfma(double a, double b, cb_d4 c) {
 __device__ inline void cb_sub_abh_mfma(const double* Ar, const double* Ai, const double* Br, const double* Bi,
                                        double* Or, double* Oi, int lane) {
     const int m = lane & 15, q = lane >> 4;
-    cb_d4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    // four independent accumulator chains, so that consecutive matrix-core
+    // operations never wait on each other's result
+    cb_d4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0}, er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
+    double ar[4], ai[4], br[4], bi[4];
 #pragma unroll
-    for (int kk = 0; kk < CB; kk += 4) {
-        const int ia = m + CB * (kk + q);   // A[m][kk+q]; B^H[kk+q][m] = conj(B[m][kk+q])
-        const double ar = Ar[ia], ai = Ai[ia], br = Br[ia], bi = Bi[ia];
-        dr = cb_mfma(ar, br, dr);
-        dr = cb_mfma(ai, bi, dr);
-        di = cb_mfma(ai, br, di);
-        di = cb_mfma(-ar, bi, di);
+    for (int t = 0; t < 4; ++t) {
+        const int ia = m + CB * (4 * t + q);   // A[m][kk+q]; B^H[kk+q][m] = conj(B[m][kk+q])
+        ar[t] = Ar[ia];
+        ai[t] = Ai[ia];
+        br[t] = Br[ia];
+        bi[t] = Bi[ia];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        dr = cb_mfma(ar[t], br[t], dr);
+        di = cb_mfma(ai[t], br[t], di);
+        er = cb_mfma(ai[t], bi[t], er);
+        ei = cb_mfma(-ar[t], bi[t], ei);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int o = (q + 4 * r) + CB * m;
-        Or[o] -= dr[r];
-        Oi[o] -= di[r];
+        Or[o] -= dr[r] + er[r];
+        Oi[o] -= di[r] + ei[r];
     }
 }
 
@@ -1709,15 +1718,14 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                 s_im[e] = gim[q];
             }
         }
-        // blocks strictly above the diagonal of an in-place inverse are zero
+        // blocks strictly above the diagonal of an in-place inverse are zero:
+        // rows 0 .. 16 (j / 16) - 1 of column j
         if (direct)
-            for (int64_t e = tid; e < DD; e += CB_THREADS) {
-                const int i = (int)(e % D), j = (int)(e / D);
-                if ((i >> 4) < (j >> 4)) {
-                    Linv[e] = 0.0;
-                    Linv[DD + e] = 0.0;
+            for (int j = wave; j < D; j += CB_WAVES)
+                for (int i = lane; i < CB * (j / CB); i += 64) {
+                    Linv[i + (int64_t)D * j] = 0.0;
+                    Linv[DD + i + (int64_t)D * j] = 0.0;
                 }
-            }
     }
     __syncthreads();
     int bad = 0;
@@ -1823,7 +1831,8 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                 xa_r[j] = Xr[g];
                 xa_i[j] = Xi[g];
             }
-            cb_d4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+            // four independent accumulator chains (T = tr + ur, ti + ui)
+            cb_d4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0}, ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
 #pragma unroll
             for (int t = 0; t < CB_MAXNB - 1; ++t) {
                 if (t < dl) {
@@ -1834,21 +1843,25 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                         const int ia = m + CB * (4 * j + q);
                         const double lr = Lr[ia], li = Li[ia], br = xb_r[4 * t + j], bi = xb_i[4 * t + j];
                         tr = cb_mfma(lr, br, tr);
-                        tr = cb_mfma(-li, bi, tr);
                         ti = cb_mfma(lr, bi, ti);
-                        ti = cb_mfma(li, br, ti);
+                        ur = cb_mfma(-li, bi, ur);
+                        ui = cb_mfma(li, br, ui);
                     }
                 }
             }
+            tr += ur;
+            ti += ui;
             // X_IJ = - X_II T: the output layout of T is the B fragment layout
-            cb_d4 orr = {0, 0, 0, 0}, oi = {0, 0, 0, 0};
+            cb_d4 orr = {0, 0, 0, 0}, oi = {0, 0, 0, 0}, o2r = {0, 0, 0, 0}, o2i = {0, 0, 0, 0};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 orr = cb_mfma(-xa_r[j], tr[j], orr);
-                orr = cb_mfma(xa_i[j], ti[j], orr);
                 oi = cb_mfma(-xa_r[j], ti[j], oi);
-                oi = cb_mfma(-xa_i[j], tr[j], oi);
+                o2r = cb_mfma(xa_i[j], ti[j], o2r);
+                o2i = cb_mfma(-xa_i[j], tr[j], o2i);
             }
+            orr += o2r;
+            oi += o2i;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t g = (CB * I + q + 4 * r) + (int64_t)Dp * (CB * J + m);
