@@ -681,7 +681,7 @@ def summarize_profile(profdir, calib_mib=256, out_dir=None):
     out_dir = out_dir or os.path.join(ROOT, "profiles")
     written = []
     base = ("--steps 1 --warmup 1 --no-fp64 --no-cpu --adjoint-steps 0 --sample-shots 0 --open-gamma 0 "
-            "--bf16-steps 0 --calib-copy-mib 256")
+            "--bf16-steps 0 --two-site-steps 0 --calib-copy-mib 256")
     tdir = os.path.join(profdir, "trace")
     if os.path.isdir(tdir):
         t = _trace_summary(tdir, os.path.join(tdir, "launches.json"))
