@@ -494,49 +494,40 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void k_cgemm_mfma(Gemm<R> g, 
             }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 // ---------------------------------------------------------------------------
 // BF16-split contraction (precision mode BF16x3): FP32 operands, every real
 // product from bf16 pieces x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) as
 // hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
-// (about 16 bits of each operand; relative error near 2^-16 per product),
-// combined into complex products by the same three-product form.  The tile
-// is staged once per 32-wide k-tile as six bf16 planes per operand (Re, Im,
-// Re + Im, each hi and lo), k-contiguous so that a lane reads its eight k
-// values with one 16-byte LDS load; single-buffered LDS, the next k-tile is
-// fetched into registers during the current one's products.  Operand lane
-// layout of the 16x16x32 instruction: lane l holds k = 8 (l / 16) .. +7 of
-// row (A) or column (B) l % 16; the output layout is that of 16x16x4.
-// Tiles are 128 x 128 over 8 waves (each wave 64 x 32, 120 KB of LDS, one
-// block per CU): with 64 x 128 tiles (about 5 complex multiply-adds per
-// operand byte fetched) the waves waited on operand fetch, and 128 x 128
-// tiles (8 per byte) measured 20-30% faster.
+// (about 16 bits of each operand; relative error near 2^-16 per product).
+// The complex product takes the four real products (Re Re, Im Im, Re Im,
+// Im Re): each operand is staged as four bf16 planes (Re hi, Re lo, Im hi,
+// Im lo), so a matrix-core operation needs a third fewer LDS fragment bytes
+// than the three-product form, whose Re + Im sums add two more planes (that
+// form measured 4-13% slower on the 128^3 stages, and its sums cost accuracy:
+// relative error 1e-5 against 5e-6).  Operand lane layout of the 16x16x32
+// instruction: lane l holds k = 8 (l / 16) .. +7 of row (A) or column (B)
+// l % 16; the output layout is that of 16x16x4.  A 128 x 128 block tile
+// over WGM x WGN waves.  LDS rows are 32 bf16 (64 bytes) with the four 16-byte
+// k-chunks of a row permuted by (row / 4) mod 4, so that the 16 rows of a
+// fragment read fall on distinct banks; two buffers of 64 KB let the next
+// k-tile be stashed while the current one is multiplied (one barrier per
+// k-tile).
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-template <int BM, int BN, int WGM, int WGN, bool AK, bool BKF>
+template <int WGM, int WGN, bool AK, bool BKF>
 __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> g, int tilesM, int tilesN,
-                                                                  int splits, int kchunk, float* partial,
-                                                                  int vec) {
+                                                                    int splits, int kchunk, float* partial, int vec) {
     if (g.skip && *g.skip) return;
-    constexpr int NT = 64 * WGM * WGN;
-    constexpr int BK = 32, KP = BK + 8;   // row stride in bf16: 80 bytes, 16-byte aligned rows
+    constexpr int BM = 128, BN = 128, NT = 64 * WGM * WGN, BK = 32;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TI = WM / 16, TJ = WN / 16;
-    static_assert(TI >= 1 && TJ >= 1, "wave tile below 16 x 16");
-    // Each thread stages four consecutive k of one row and writes them with
-    // one 64-bit LDS store per plane. Rows sit 20 dwords apart, so eight
-    // consecutive rows start on eight different 4-bank groups; for an
-    // index-fast operand lanes 0-7 take rows r..r+7 at k-quad q and lanes 8-15
-    // the same rows at q+1, which fills every bank once per 16 lanes, and a
-    // wavefront's global loads still cover 32 consecutive rows per k. For a
-    // k-fast operand eight lanes walk the 32 k of one row, and the rows of the
-    // 8-lane groups step by 4 (80 dwords, half the banks) so that 16 or 32
-    // lanes again touch every bank once.
     constexpr int QA = BM * BK / (4 * NT), QB = BN * BK / (4 * NT);
     static_assert(QA >= 1 && QB >= 1, "tile smaller than the block");
     typedef f32x4 acc_t;
-    __shared__ __attribute__((aligned(16))) __bf16 As[6][BM][KP];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[6][BN][KP];
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][4][BM][BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][4][BN][BK];
     int64_t bid = blockIdx.x;
     const int tm = bid % tilesM;
     bid /= tilesM;
@@ -556,24 +547,28 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> 
     const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
     const float sa = g.conjA ? -1.0f : 1.0f, sb = g.conjB ? -1.0f : 1.0f;
     const int mlim = g.M - m0, nlim = g.N - n0;
-    // slot e of an R-row tile -> row and k-quad (k = 4 kq .. 4 kq + 3)
-    auto slot = [&](int e, int R, bool kfast, int& row, int& kq) {
+    // slot e (< 1024) of a 128-row tile -> row and k-quad (k = 4 kq .. 4 kq +
+    // 3): a k-fast operand takes eight consecutive slots per row (one row =
+    // 128 contiguous bytes); an index-fast one takes 32 consecutive rows per
+    // k pair
+    auto slot = [&](int e, bool kfast, int& row, int& kq) {
         if (kfast) {
-            const int j = e / (BK / 4);
+            row = e / (BK / 4);
             kq = e % (BK / 4);
-            row = 4 * (j % 4) + (j / 4) % 4 + 16 * (j / 16);
         } else {
-            const int rest = e / 16;
-            row = e % 8 + 8 * (rest % (R / 8));
-            kq = (e / 8) % 2 + 2 * (rest / (R / 8));
+            row = e % 32 + 32 * ((e / 64) % 4);
+            kq = (e / 32) % 2 + 2 * (e / 256);
         }
     };
+    // element offset of (row, k) inside a [rows][32] plane: the 16-byte chunk
+    // k / 8 moves to chunk (k / 8) ^ ((row / 4) % 4)
+    auto lds_off = [](int row, int k) { return row * BK + ((((k >> 3) ^ (row >> 2)) & 3) << 3) + (k & 7); };
     int offA[QA], offB[QB];
     float mA[QA], mB[QB];
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
         int mm, kq;
-        slot(tid + NT * q, BM, AK, mm, kq);
+        slot(tid + NT * q, AK, mm, kq);
         const bool ok = mm < mlim;
         mA[q] = ok ? 1.0f : 0.0f;
         offA[q] = (ok ? mm : 0) * (int)g.sam + 4 * kq * (int)g.sak;
@@ -581,114 +576,132 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> 
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
         int nn, kq;
-        slot(tid + NT * q, BN, BKF, nn, kq);
+        slot(tid + NT * q, BKF, nn, kq);
         const bool ok = nn < nlim;
         mB[q] = ok ? 1.0f : 0.0f;
         offB[q] = (ok ? nn : 0) * (int)g.sbn + 4 * kq * (int)g.sbk;
     }
-    constexpr int QM = QA > QB ? QA : QB;
-    float pa[8][QM], pb[8][QM];   // [re k .. k+3, im k .. k+3]
+    float pa[8][QA], pb[8][QB];   // [re k .. k+3, im k .. k+3]
     auto fetch = [&](int k0) {
         const int kin = k0 % g.Kin, kout = k0 / g.Kin;
         const float* Ab = A + (int64_t)kin * g.sak + (int64_t)kout * g.sako;
         const float* Bb = B + (int64_t)kin * g.sbk + (int64_t)kout * g.sbko;
         const int ka = (int)g.sak, kbs = (int)g.sbk;
-        // a k-fast quad is one 16-byte load where the host found it aligned
-        auto quad = [&](const float* src, int stride, bool v, float scale, float (*dst)[QM], int q) {
-            if (v) {
-                const float4 t = *(const float4*)src;
-                dst[0][q] = scale * t.x;
-                dst[1][q] = scale * t.y;
-                dst[2][q] = scale * t.z;
-                dst[3][q] = scale * t.w;
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) dst[j][q] = scale * src[j * stride];
-            }
-        };
         const bool va = AK && (vec & 1), vb = BKF && (vec & 2);
 #pragma unroll
-        for (int q = 0; q < QA; ++q) {
-            quad(Ab + offA[q], ka, va, mA[q], pa, q);
-            quad(Ab + offA[q] + g.a_plane, ka, va, sa * mA[q], pa + 4, q);
-        }
+        for (int q = 0; q < QA; ++q)
 #pragma unroll
-        for (int q = 0; q < QB; ++q) {
-            quad(Bb + offB[q], kbs, vb, mB[q], pb, q);
-            quad(Bb + offB[q] + g.b_plane, kbs, vb, sb * mB[q], pb + 4, q);
-        }
+            for (int h = 0; h < 2; ++h) {
+                const float* src = Ab + offA[q] + (h ? g.a_plane : 0);
+                const float sc = h ? sa * mA[q] : mA[q];
+                if (va) {
+                    const float4 t4 = *(const float4*)src;
+                    pa[4 * h][q] = sc * t4.x;
+                    pa[4 * h + 1][q] = sc * t4.y;
+                    pa[4 * h + 2][q] = sc * t4.z;
+                    pa[4 * h + 3][q] = sc * t4.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) pa[4 * h + j][q] = sc * src[j * ka];
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < QB; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float* src = Bb + offB[q] + (h ? g.b_plane : 0);
+                const float sc = h ? sb * mB[q] : mB[q];
+                if (vb) {
+                    const float4 t4 = *(const float4*)src;
+                    pb[4 * h][q] = sc * t4.x;
+                    pb[4 * h + 1][q] = sc * t4.y;
+                    pb[4 * h + 2][q] = sc * t4.z;
+                    pb[4 * h + 3][q] = sc * t4.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) pb[4 * h + j][q] = sc * src[j * kbs];
+                }
+            }
     };
-    // planes 2c (hi) and 2c + 1 (lo) of value c in {Re, Im, Re + Im}, four k at once
-    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     auto put = [](__bf16* hi_dst, __bf16* lo_dst, float x0, float x1, float x2, float x3) {
         const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1, h2 = (__bf16)x2, h3 = (__bf16)x3;
         *(bf16x4*)hi_dst = bf16x4{h0, h1, h2, h3};
         *(bf16x4*)lo_dst = bf16x4{(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1), (__bf16)(x2 - (float)h2),
                                   (__bf16)(x3 - (float)h3)};
     };
-    auto stash = [&]() {
+    auto stash = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             int mm, kq;
-            slot(tid + NT * q, BM, AK, mm, kq);
-            const int kk = 4 * kq;
-            put(&As[0][mm][kk], &As[1][mm][kk], pa[0][q], pa[1][q], pa[2][q], pa[3][q]);
-            put(&As[2][mm][kk], &As[3][mm][kk], pa[4][q], pa[5][q], pa[6][q], pa[7][q]);
-            put(&As[4][mm][kk], &As[5][mm][kk], pa[0][q] + pa[4][q], pa[1][q] + pa[5][q], pa[2][q] + pa[6][q],
-                pa[3][q] + pa[7][q]);
+            slot(tid + NT * q, AK, mm, kq);
+            const int o = lds_off(mm, 4 * kq);
+            put(&As[buf][0][0][0] + o, &As[buf][1][0][0] + o, pa[0][q], pa[1][q], pa[2][q], pa[3][q]);
+            put(&As[buf][2][0][0] + o, &As[buf][3][0][0] + o, pa[4][q], pa[5][q], pa[6][q], pa[7][q]);
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             int nn, kq;
-            slot(tid + NT * q, BN, BKF, nn, kq);
-            const int kk = 4 * kq;
-            put(&Bs[0][nn][kk], &Bs[1][nn][kk], pb[0][q], pb[1][q], pb[2][q], pb[3][q]);
-            put(&Bs[2][nn][kk], &Bs[3][nn][kk], pb[4][q], pb[5][q], pb[6][q], pb[7][q]);
-            put(&Bs[4][nn][kk], &Bs[5][nn][kk], pb[0][q] + pb[4][q], pb[1][q] + pb[5][q], pb[2][q] + pb[6][q],
-                pb[3][q] + pb[7][q]);
+            slot(tid + NT * q, BKF, nn, kq);
+            const int o = lds_off(nn, 4 * kq);
+            put(&Bs[buf][0][0][0] + o, &Bs[buf][1][0][0] + o, pb[0][q], pb[1][q], pb[2][q], pb[3][q]);
+            put(&Bs[buf][2][0][0] + o, &Bs[buf][3][0][0] + o, pb[4][q], pb[5][q], pb[6][q], pb[7][q]);
         }
     };
-    acc_t c1[TI][TJ], c2[TI][TJ], c3[TI][TJ];
+    acc_t crr[TI][TJ], cii[TI][TJ], cim[TI][TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
-            c1[i][j] = acc_t{0, 0, 0, 0};
-            c2[i][j] = acc_t{0, 0, 0, 0};
-            c3[i][j] = acc_t{0, 0, 0, 0};
+            crr[i][j] = acc_t{0, 0, 0, 0};
+            cii[i][j] = acc_t{0, 0, 0, 0};
+            cim[i][j] = acc_t{0, 0, 0, 0};
         }
     const int nt = (ke - kb) / BK;
     const int kg = 8 * (lane / 16), c16 = lane % 16;
-    if (nt > 0) fetch(kb);
+    if (nt > 0) {
+        fetch(kb);
+        stash(0);
+        if (nt > 1) fetch(kb + BK);
+    }
+    __syncthreads();
     for (int t = 0; t < nt; ++t) {
-        __syncthreads();   // the previous tile's fragment reads are done
-        stash();
-        __syncthreads();
-        if (t + 1 < nt) fetch(kb + (t + 1) * BK);
-        bf16x8 bf[TJ][6];
+        const int cur = t & 1;
+        bf16x8 bf[TJ][4];
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
+        for (int j = 0; j < TJ; ++j) {
+            const int o = lds_off(wn0 + 16 * j + c16, kg);
 #pragma unroll
-            for (int p = 0; p < 6; ++p) bf[j][p] = *(const bf16x8*)&Bs[p][wn0 + 16 * j + c16][kg];
+            for (int p = 0; p < 4; ++p) bf[j][p] = *(const bf16x8*)(&Bs[cur][p][0][0] + o);
+        }
 #pragma unroll
         for (int i = 0; i < TI; ++i) {
-            bf16x8 af[6];
+            bf16x8 af[4];
+            const int o = lds_off(wm0 + 16 * i + c16, kg);
 #pragma unroll
-            for (int p = 0; p < 6; ++p) af[p] = *(const bf16x8*)&As[p][wm0 + 16 * i + c16][kg];
+            for (int p = 0; p < 4; ++p) af[p] = *(const bf16x8*)(&As[cur][p][0][0] + o);
 #pragma unroll
             for (int j = 0; j < TJ; ++j) {
-                // P1 = Re A Re B, P2 = Im A Im B, P3 = (Re + Im) A (Re + Im) B, each hi*hi + hi*lo + lo*hi
-                c1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[0], c1[i][j], 0, 0, 0);
-                c2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[2], c2[i][j], 0, 0, 0);
-                c3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][4], af[4], c3[i][j], 0, 0, 0);
-                c1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][1], af[0], c1[i][j], 0, 0, 0);
-                c2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][3], af[2], c2[i][j], 0, 0, 0);
-                c3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][5], af[4], c3[i][j], 0, 0, 0);
-                c1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[1], c1[i][j], 0, 0, 0);
-                c2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[3], c2[i][j], 0, 0, 0);
-                c3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][4], af[5], c3[i][j], 0, 0, 0);
+                // planes: 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo; each real product
+                // hi*hi + lo*hi + hi*lo
+                crr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[0], crr[i][j], 0, 0, 0);
+                cii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[2], cii[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[0], cim[i][j], 0, 0, 0);
+                crr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][1], af[0], crr[i][j], 0, 0, 0);
+                cii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][3], af[2], cii[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][3], af[0], cim[i][j], 0, 0, 0);
+                crr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[1], crr[i][j], 0, 0, 0);
+                cii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[3], cii[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][2], af[1], cim[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[2], cim[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][1], af[2], cim[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j][0], af[3], cim[i][j], 0, 0, 0);
             }
         }
+        if (t + 1 < nt) {
+            stash(cur ^ 1);
+            if (t + 2 < nt) fetch(kb + (t + 2) * BK);
+        }
+        __syncthreads();
     }
     const int64_t MN = (int64_t)g.M * g.N;
     const int nbatch = g.B1 * g.B2;
@@ -703,8 +716,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void k_cgemm_bf16x3(Gemm<float> 
                 const int m = m0 + wm0 + 16 * i + c16;
                 const int n = n0 + wn0 + 16 * j + 4 * (lane / 16) + r;
                 if (m >= g.M || n >= g.N) continue;
-                const float vre = c1[i][j][r] - c2[i][j][r];
-                const float vim = c3[i][j][r] - c1[i][j][r] - c2[i][j][r];
+                const float vre = crr[i][j][r] - cii[i][j][r];
+                const float vim = cim[i][j][r];
                 if (splits == 1) {
                     const int64_t off = (int64_t)m * g.scm + (int64_t)n * g.scn;
                     float re = g.alpha * vre, im = g.alpha * vim;
@@ -859,27 +872,25 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
         // large tiles: 16 waves (4 x 4) per block, one block per CU (FP32 waves
         // own 32 x 32 outputs, FP64 waves 32 x 16); small tiles: 4 waves
         // (2 x 2), two blocks per CU
-#define TTN_BF16_LAUNCH(bm, bn, wgm, wgn)                                                                   \
-    do {                                                                                                   \
-        const dim3 blk(64 * wgm * wgn);                                                                    \
-        if (a_k && b_k)                                                                                    \
-            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, true, true>), grid, blk, 0, s, g, tilesM,   \
-                               tilesN, splits, kchunk, part, vec);                                              \
-        else if (a_k)                                                                                      \
-            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, true, false>), grid, blk, 0, s, g, tilesM,  \
-                               tilesN, splits, kchunk, part, vec);                                              \
-        else if (b_k)                                                                                      \
-            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, false, true>), grid, blk, 0, s, g, tilesM,  \
-                               tilesN, splits, kchunk, part, vec);                                              \
-        else                                                                                               \
-            hipLaunchKernelGGL((k_cgemm_bf16x3<bm, bn, wgm, wgn, false, false>), grid, blk, 0, s, g, tilesM, \
-                               tilesN, splits, kchunk, part, vec);                                              \
-    } while (0)
         if constexpr (sizeof(R) == 4) {
             // BF16x3 mode: the large tiles with 32-wide k-tiles take the split
             // products; the small shapes stay FP32
-            if (bf16)
-                TTN_BF16_LAUNCH(128, 128, 2, 4);
+            if (bf16) {
+                // 8 waves (2 x 4) of 64 x 32 outputs
+                const dim3 blk(512);
+                if (a_k && b_k)
+                    hipLaunchKernelGGL((k_cgemm_bf16x3<2, 4, true, true>), grid, blk, 0, s, g, tilesM, tilesN,
+                                       splits, kchunk, part, vec);
+                else if (a_k)
+                    hipLaunchKernelGGL((k_cgemm_bf16x3<2, 4, true, false>), grid, blk, 0, s, g, tilesM, tilesN,
+                                       splits, kchunk, part, vec);
+                else if (b_k)
+                    hipLaunchKernelGGL((k_cgemm_bf16x3<2, 4, false, true>), grid, blk, 0, s, g, tilesM, tilesN,
+                                       splits, kchunk, part, vec);
+                else
+                    hipLaunchKernelGGL((k_cgemm_bf16x3<2, 4, false, false>), grid, blk, 0, s, g, tilesM, tilesN,
+                                       splits, kchunk, part, vec);
+            }
             else if (BM == 128 && kq == 32)
                 TTN_MFMA_LAUNCH(128, 128, 4, 4, 1, 32);
             else if (BM == 128)
@@ -893,7 +904,6 @@ bool cgemm(const Gemm<R>& g, const GemmScratch& ws, hipStream_t s, char* why, in
                 TTN_MFMA_LAUNCH(64, 64, 2, 2, 2, 16);
         }
 #undef TTN_MFMA_LAUNCH
-#undef TTN_BF16_LAUNCH
         if (splits > 1) {
             splitk_reduce(g, splits, (const R*)ws.partial, s);
         }

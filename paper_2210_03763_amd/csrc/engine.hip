@@ -850,10 +850,11 @@ void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
         chk(h, o.Wb, 2 * (1 + o.sL + o.sR) * P2, "W stack");
         chk(h, h->Wf, (1 + o.sL + o.sR) * P2, "W stack fp32");
     }
-    convert_d2f(o.Lb, h->Lf, 2 * (1 + o.sL) * L2, skip, h->stream);
-    if (o.Rb) convert_d2f(o.Rb, h->Rf, 2 * (1 + o.sR) * R2, skip, h->stream);
-    if (o.Bb) convert_d2f(o.Bb, h->Bf, 2 * (1 + o.sL) * R2, skip, h->stream);
-    if (o.Wb) convert_d2f(o.Wb, h->Wf, 2 * (1 + o.sL + o.sR) * P2, skip, h->stream);
+    convert_d2f_many({{o.Lb, h->Lf, 2 * (1 + o.sL) * L2},
+                      {o.Rb, h->Rf, 2 * (1 + o.sR) * R2},
+                      {o.Bb, h->Bf, 2 * (1 + o.sL) * R2},
+                      {o.Wb, h->Wf, 2 * (1 + o.sL + o.sR) * P2}},
+                     skip, h->stream);
 }
 
 // staged: the mixed-precision matvec whose input is already in the FP32 slot
@@ -1161,10 +1162,11 @@ void build_up(ttn_handle* h, int v) {
         Ctx<float> cf{h, nullptr};
         float* Qf = h->Xf;   // slot 0 of the FP32 stack is free during an environment build
         chk(h, h->Ef, (1 + sL + sR) * P2, "fp32 environment staging");
-        convert_d2f(h->T[v], Qf, 2 * n, nullptr, h->stream);
-        convert_d2f(Lb, h->Lf, 2 * (1 + sL) * L2, nullptr, h->stream);
-        convert_d2f(Rb, h->Rf, 2 * (1 + sR) * R2, nullptr, h->stream);
-        convert_d2f(h->Bstk, h->Bf, 2 * (1 + sL) * R2, nullptr, h->stream);
+        convert_d2f_many({{h->T[v], Qf, 2 * n},
+                          {Lb, h->Lf, 2 * (1 + sL) * L2},
+                          {Rb, h->Rf, 2 * (1 + sR) * R2},
+                          {h->Bstk, h->Bf, 2 * (1 + sL) * R2}},
+                         nullptr, h->stream);
         build_up_core<float>(cf, DL, DR, DP, sL, sR, Qf, h->Lf, h->Rf, h->Bf, h->Xf, h->Yf, h->Ef);
         herm_f2d(h->Ef, h->up[v], DP, 1 + sL + sR, h->stream, h->nonherm);
     } else {
@@ -1201,14 +1203,13 @@ void build_down(ttn_handle* h, int cnode) {
         Ctx<float> cf{h, nullptr};
         float* Qf = h->Xf;
         chk(h, h->Ef, (1 + (leg == 0 ? sL : sR)) * C2, "fp32 environment staging");
-        convert_d2f(h->T[u], Qf, 2 * n, nullptr, h->stream);
-        convert_d2f(Lb, h->Lf, 2 * (1 + sL) * L2, nullptr, h->stream);
-        convert_d2f(Rb, h->Rf, 2 * (1 + sR) * R2, nullptr, h->stream);
-        if (Wb) convert_d2f(Wb, h->Wf, 2 * (1 + sL + sR) * P2, nullptr, h->stream);
-        if (leg == 0)
-            convert_d2f(Ab, h->Bf, 2 * Alen, nullptr, h->stream);
-        else
-            convert_d2f(Ab + 2 * L2, h->Bf + 2 * L2, 2 * (Alen - L2), nullptr, h->stream);
+        convert_d2f_many({{h->T[u], Qf, 2 * n},
+                          {Lb, h->Lf, 2 * (1 + sL) * L2},
+                          {Rb, h->Rf, 2 * (1 + sR) * R2},
+                          {Wb, h->Wf, 2 * (1 + sL + sR) * P2},
+                          leg == 0 ? D2FItem{Ab, h->Bf, 2 * Alen}
+                                   : D2FItem{Ab + 2 * L2, h->Bf + 2 * L2, 2 * (Alen - L2)}},
+                         nullptr, h->stream);
         build_down_core<float>(cf, leg, DL, DR, DP, sL, sR, Qf, h->Lf, h->Rf, Wb ? h->Wf : nullptr, h->Bf, h->Xf,
                                h->Yf, h->Ef);
         herm_f2d(h->Ef, h->dn[cnode], Dc, 1 + (leg == 0 ? sL : sR), h->stream, h->nonherm);

@@ -5,6 +5,8 @@
 // conversions and small helpers.
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
+
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -1137,6 +1139,22 @@ __global__ void k_d2f(const double* x, float* y, int64_t c, const int* skip) {
          i += (int64_t)gridDim.x * blockDim.x)
         y[i] = (float)x[i];
 }
+
+// several conversions in one launch: the concatenated index space of the
+// arrays, each element converted exactly as by k_d2f
+__global__ void k_d2f_batch(D2FBatch b, int64_t total, const int* skip) {
+    if (skip && *skip) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int k = 0;
+        int64_t off = i;
+        while (k < b.n - 1 && off >= b.c[k]) {
+            off -= b.c[k];
+            ++k;
+        }
+        b.y[k][off] = (float)b.x[k][off];
+    }
+}
 __global__ void k_f2d(const float* x, double* y, int64_t c, const int* skip) {
     if (skip && *skip) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c;
@@ -1206,6 +1224,25 @@ void sum_mats(const double* src, int D, int count, double* dst, hipStream_t s) {
 void convert_d2f(const double* x, float* y, int64_t count, const int* skip, hipStream_t s) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_d2f, dim3(grid_for(count)), dim3(256), 0, s, x, y, count, skip);
+}
+void convert_d2f_many(std::initializer_list<D2FItem> items, const int* skip, hipStream_t s) {
+    if (g_dry_run) return;
+    D2FBatch b{};
+    int64_t total = 0;
+    for (const D2FItem& it : items) {
+        if (!it.x || it.count <= 0) continue;
+        if (b.n == D2F_MAX) {   // full: flush
+            hipLaunchKernelGGL(k_d2f_batch, dim3(grid_for(total)), dim3(256), 0, s, b, total, skip);
+            b = D2FBatch{};
+            total = 0;
+        }
+        b.x[b.n] = it.x;
+        b.y[b.n] = it.y;
+        b.c[b.n] = it.count;
+        ++b.n;
+        total += it.count;
+    }
+    if (b.n > 0) hipLaunchKernelGGL(k_d2f_batch, dim3(grid_for(total)), dim3(256), 0, s, b, total, skip);
 }
 void convert_f2d(const float* x, double* y, int64_t count, const int* skip, hipStream_t s) {
     if (g_dry_run) return;

@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
+
 #include <cstdint>
 
 namespace ttn {
@@ -146,6 +148,20 @@ void lz_combine(const double* V, int64_t n, double* out, LanczosDev* lz, hipStre
 
 // conversions and copies
 void convert_d2f(const double* x, float* y, int64_t count, const int* skip, hipStream_t s);
+// several FP64 -> FP32 conversions in one launch (null or empty items skipped)
+struct D2FItem {
+    const double* x;
+    float* y;
+    int64_t count;
+};
+constexpr int D2F_MAX = 6;
+struct D2FBatch {
+    const double* x[D2F_MAX];
+    float* y[D2F_MAX];
+    int64_t c[D2F_MAX];
+    int n;
+};
+void convert_d2f_many(std::initializer_list<D2FItem> items, const int* skip, hipStream_t s);
 void convert_f2d(const float* x, double* y, int64_t count, const int* skip, hipStream_t s);
 void copy_d(const double* x, double* y, int64_t count, const int* skip, hipStream_t s);
 void transpose_c(const double* x, double* y, int rows, int cols, hipStream_t s);
