@@ -301,7 +301,8 @@ void plan(ttn_handle* h, Bump& b) {
     h->d_leaf_site = b.take<int>(h->N);
     h->X = b.take<double>(2 * h->stack_max);
     h->W = b.take<double>(2 * nvec);
-    h->Vk = b.take<double>(2 * nvec * (h->m + 1));
+    // planar bases (small path, n <= LZ_SMALL_N) or chunked ones: padded to whole chunks
+    h->Vk = b.take<double>(2 * kch_pad(nvec) * (h->m + 1));
     h->Qtmp = b.take<double>(2 * nqr);
     h->Ttmp = b.take<double>(2 * h->nmax);
     if (h->two_site) {
@@ -858,9 +859,10 @@ void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
 }
 
 // staged: the mixed-precision matvec whose input is already in the FP32 slot
-// (h->Xf) and whose output stays in h->Yf (the Lanczos kernels convert)
+// (h->Xf) and whose output stays in h->Yf (the Lanczos kernels convert).
+// xS != 0: x is a slot of a chunked Krylov basis with that chunk stride.
 void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, const int* skip,
-                   bool force_fp64 = false, bool staged = false) {
+                   bool force_fp64 = false, bool staged = false, int64_t xS = 0) {
     const int64_t n = (int64_t)o.DL * o.DR * o.DP;
     // marks the contraction launches of one matvec; in a timed profiling
     // window one event pair brackets them (no events between its launches)
@@ -887,16 +889,26 @@ void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, c
             }
         }
     };
+    // the FP64 input slot: a copy of x, or its planar image when x is chunked
+    auto to_slot0 = [&]() {
+        if (xS)
+            krylov_unchunk(x, xS, n, 1, h->X, skip, h->stream);
+        else
+            copy_d(x, h->X, 2 * n, skip, h->stream);
+    };
     if (o.e2) {   // two-site update: FP64
         Ctx<double> c{h, skip};
-        copy_d(x, h->X, 2 * n, skip, h->stream);
+        to_slot0();
         HeffMark mark(h);
         apply_op2(c, *o.e2, h->X, y);
         return;
     }
     if (h->prec == TTN_PREC_FP32 && !force_fp64) {
         Ctx<float> c{h, skip};
-        if (!staged) convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
+        if (!staged) {
+            if (xS) throw StatusError{TTN_ENOTSUP, "unstaged mixed matvec on a chunked basis slot"};
+            convert_d2f(x, h->Xf, 2 * n, skip, h->stream);
+        }
         {
             HeffMark mark(h);
             apply_op<float>(c, o, h->Lf, o.Rb ? h->Rf : nullptr, o.Bb ? h->Bf : nullptr,
@@ -905,10 +917,16 @@ void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, c
         if (!staged) convert_f2d(h->Yf, y, 2 * n, skip, h->stream);
     } else {
         Ctx<double> c{h, skip};
-        copy_d(x, h->X, 2 * n, skip, h->stream);
+        to_slot0();
         HeffMark mark(h);
         apply_op<double>(c, o, o.Lb, o.Rb, o.Bb, o.Wb, h->X, y);
     }
+}
+
+// chunk stride of the Krylov basis of an operator of n entries: the general
+// path stores it in chunks (0: the planar basis of the small path)
+int64_t krylov_stride(const ttn_handle* h, int64_t n) {
+    return n > LZ_SMALL_N ? 2 * (int64_t)KCH * (h->m + 1) : 0;
 }
 
 // x <- exp(-i tau Op) x by Lanczos (full re-orthogonalisation, device scalars)
@@ -919,8 +937,9 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     const int nb = (int)std::min<int64_t>(RED_BLOCKS, (n + 255) / 256);
     hipStream_t s = h->stream;
     LanczosDev* lz = h->lz;
+    const int64_t S = krylov_stride(h, n);
     chk(h, x, 2 * n, "krylov input");
-    chk(h, h->Vk, 2 * n * (h->m + 1), "krylov basis");
+    chk(h, h->Vk, 2 * (S ? kch_pad(n) : n) * (h->m + 1), "krylov basis");
     chk(h, h->W, 2 * n, "krylov work vector");
     chk(h, h->X, 2 * n, "stack slot 0");
     if (h->prec == TTN_PREC_FP32) {
@@ -935,7 +954,7 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     const double E = 16.0 * (double)n, Ef = xf ? 8.0 * (double)n : 0.0;
     {
         VecTimer t(h, 3 * E + Ef, n);   // norm of x, then v0 = x / |x| (+ its FP32 copy)
-        lz_start(x, n, h->Vk, lz, h->red, nb, s, h->nonherm ? 1 : 0, xf);
+        lz_start(x, n, h->Vk, S, lz, h->red, nb, s, h->nonherm ? 1 : 0, xf);
     }
     if (n <= LZ_SMALL_N) {
         for (int j = 0; j < h->m; ++j) {
@@ -949,26 +968,26 @@ void lanczos_basis(ttn_handle* h, const OpDesc& o, const double* x) {
     const bool fuse = nb <= LZ_FUSE_NB;
     static_assert((int64_t)RED_BLOCKS * KRYLOV_MAX * 2 >= 2 * LZ_PARTIAL_HALF, "reduction buffer too small");
     for (int j = 0; j < h->m; ++j) {
-        double* vj = h->Vk + 2 * n * j;
-        apply_op_prec(h, o, vj, h->W, &lz->done, false, xf != nullptr);
+        double* vj = h->Vk + 2 * KCH * j;
+        apply_op_prec(h, o, vj, h->W, &lz->done, false, xf != nullptr, S);
         // classical Gram-Schmidt, two passes: the first projection also gives alpha_j
         const bool last = j == h->m - 1;
         const double kc = j + 1;
         {
             // V^H w over j + 1 vectors; w read, or widened from the FP32 matvec output
             VecTimer t(h, kc * E + (xf ? 0.5 * E + E : E), n);
-            lz_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, j, s, xf ? h->Yf : nullptr, last || !fuse);
+            lz_project(h->Vk, S, j + 1, h->W, n, h->red, nb, lz, j, s, xf ? h->Yf : nullptr, last || !fuse);
         }
         if (last) break;
         {
             VecTimer t(h, kc * E + 2 * E, n);   // w -= V c and V^H w in one pass (w read and written)
-            lz_subtract_project(h->Vk, j + 1, h->W, n, h->red, nb, lz, s, fuse);
+            lz_subtract_project(h->Vk, S, j + 1, h->W, n, h->red, nb, lz, s, fuse);
         }
         {
             // w -= V c' with |w|^2, then v_{j+1} = w / beta_j (+ its FP32 copy)
             VecTimer t(h, kc * E + 2 * E + 2 * E + Ef, n);
-            lz_subtract_next(h->Vk, j + 1, h->W, n, h->Vk + 2 * n * (j + 1), lz, j, h->red, nb, LANCZOS_TOL, s,
-                             xf, fuse);
+            lz_subtract_next(h->Vk, S, j + 1, h->W, n, h->Vk + 2 * KCH * (j + 1), lz, j, h->red, nb, LANCZOS_TOL,
+                             s, xf, fuse);
         }
     }
 }
@@ -1005,7 +1024,7 @@ void lanczos_expm(ttn_handle* h, const OpDesc& o, double* x, double tau) {
     lanczos_basis(h, o, x);
     lz_expm(h->lz, tau, h->st, h->stream);
     VecTimer t(h, 16.0 * (double)n * (h->m + 1), n);   // x = |x| V y: m basis vectors read, x written
-    lz_combine(h->Vk, n, x, h->lz, h->stream);
+    lz_combine(h->Vk, krylov_stride(h, n), n, x, h->lz, h->stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1650,7 +1669,7 @@ void canonicalise(ttn_handle* h) {
     const int r = h->root;
     const int64_t n = nsize(h, r);
     const int nb = (int)std::min<int64_t>(RED_BLOCKS, (n + 255) / 256);
-    lz_start(h->T[r], n, h->T[r], h->lz_obs, h->red, nb, h->stream);
+    lz_start(h->T[r], n, h->T[r], 0, h->lz_obs, h->red, nb, h->stream);
 }
 
 void reset_step_dev(ttn_handle* h) {
@@ -1669,7 +1688,7 @@ void dot_c(ttn_handle* h, const double* x, const double* y, int64_t n, double ou
     chk(h, x, 2 * n, "dot x");
     chk(h, y, 2 * n, "dot y");
     h2d(h, h->lz_obs, &h->h_lzinit, sizeof(LanczosDev));
-    lz_project(x, 1, y, n, h->red, nb, h->lz_obs, -1, h->stream);
+    lz_project(x, 0, 1, y, n, h->red, nb, h->lz_obs, -1, h->stream);
     d2h(h, &h->h_lzout, h->lz_obs, sizeof(LanczosDev));
     sync(h);
     out[0] = h->h_lzout.c[0];

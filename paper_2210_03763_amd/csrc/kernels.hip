@@ -126,12 +126,6 @@ __device__ inline double wave_sum_partials(const double* partial, int nb) {
     return s;   // valid in lane 0
 }
 
-__global__ void k_sum_partial(const double* partial, int nb, double* out, const int* skip) {
-    if (skip && *skip) return;
-    const double s = wave_sum_partials(partial, nb);
-    if (threadIdx.x == 0) *out = s;
-}
-
 __global__ void k_lz_begin(const double* partial, int nb, LanczosDev* lz, int nonherm) {
     const double s = wave_sum_partials(partial, nb);
     if (threadIdx.x == 0) {
@@ -144,25 +138,28 @@ __global__ void k_lz_begin(const double* partial, int nb, LanczosDev* lz, int no
 }
 
 // y = x / beta (FP64), and its FP32 copy yf when yf != nullptr (the input of
-// the next mixed-precision matvec)
-__global__ void k_scale_by(const double* x, int64_t n, double* y, const LanczosDev* lz, int use_beta0,
+// the next mixed-precision matvec); y planar (S == 0) or a slot of a chunked
+// Krylov basis with chunk stride S
+__global__ void k_scale_by(const double* x, int64_t n, double* y, int64_t S, const LanczosDev* lz, int use_beta0,
                            int j, float* yf) {
     if (lz->done) return;
     const double s = 1.0 / (use_beta0 ? lz->beta0 : lz->beta[j]);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double v = x[i] * s;
-        y[i] = v;
+        y[S ? kch_elem(i, n, S) : i] = v;
         if (yf) yf[i] = (float)v;
     }
 }
 
-// v_{j+1} = w / beta_j with beta_j totalled by every block from the nb
+// v_{j+1} = w / beta_j (y planar, S == 0, or a chunked basis slot) with
+// beta_j totalled by every block from the nb
 // norm partials of k_sub_fused<2> and the breakdown test of k_lz_beta taken
 // alike in every block (block 0 records beta_j, or the breakdown); also the
 // FP32 copy yf when yf != nullptr.
-__global__ __launch_bounds__(256) void k_scale_next(const double* x, int64_t n, double* y, LanczosDev* lz,
-                                                  const double* pnorm, int nb, int j, double tol, float* yf) {
+__global__ __launch_bounds__(256) void k_scale_next(const double* x, int64_t n, double* y, int64_t S,
+                                                  LanczosDev* lz, const double* pnorm, int nb, int j, double tol,
+                                                  float* yf) {
     if (lz->done) return;
     __shared__ double sh[16];
     __shared__ double s_b;
@@ -183,7 +180,7 @@ __global__ __launch_bounds__(256) void k_scale_next(const double* x, int64_t n, 
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double v = x[i] * inv;
-        y[i] = v;
+        y[S ? kch_elem(i, n, S) : i] = v;
         if (yf) yf[i] = (float)v;
     }
 }
@@ -193,19 +190,22 @@ __global__ __launch_bounds__(256) void k_scale_next(const double* x, int64_t n, 
 // wf (and stored).  KC is a template argument so that the per-thread arrays
 // hold exactly the vectors in use.
 template <int KC, int W>
-__device__ inline void multidot_body(const double* V, const double* w, int64_t n, const float* wf, double (&re)[KC],
-                                     double (&im)[KC]) {
+__device__ inline void multidot_body(const double* V, int64_t S, const double* w, int64_t n, const float* wf,
+                                     double (&re)[KC], double (&im)[KC]) {
     // W consecutive elements per thread and step (16-byte loads for W = 2)
     typedef double dv __attribute__((ext_vector_type(W)));
     typedef float fv __attribute__((ext_vector_type(W)));
     const int64_t nw = n / W;
+    // slot and plane strides: chunked basis (S > 0) or planar vectors (S == 0)
+    const int64_t ks = S ? 2 * KCH : 2 * n, ps = S ? KCH : n;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nw; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = q * W;
+        const double* Vi = V + (S ? kch_ofs(i, S) : i);
         dv vr[KC], vi[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            vr[k] = *(const dv*)(V + 2 * n * k + i);
-            vi[k] = *(const dv*)(V + 2 * n * k + n + i);
+            vr[k] = *(const dv*)(Vi + ks * k);
+            vi[k] = *(const dv*)(Vi + ks * k + ps);
         }
         dv wr, wi;
         if (wf) {
@@ -237,7 +237,7 @@ __device__ inline void multidot_body(const double* V, const double* w, int64_t n
 // hold exactly the vectors in use; vectors of even length are read two
 // elements at a time.
 template <int KC>
-__global__ __launch_bounds__(256) void k_multidot_partial(const double* V, const double* w, int64_t n,
+__global__ __launch_bounds__(256) void k_multidot_partial(const double* V, int64_t S, const double* w, int64_t n,
                                                          double* partial, const LanczosDev* lz, const float* wf) {
     if (lz->done) return;
     constexpr int P = pow2_pairs(KC);
@@ -246,9 +246,9 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* V, const
 #pragma unroll
     for (int k = 0; k < KC; ++k) re[k] = im[k] = 0;
     if (n % 2 == 0 && (((uintptr_t)V | (uintptr_t)w | (uintptr_t)wf) & 15) == 0)
-        multidot_body<KC, 2>(V, w, n, wf, re, im);
+        multidot_body<KC, 2>(V, S, w, n, wf, re, im);
     else
-        multidot_body<KC, 1>(V, w, n, wf, re, im);
+        multidot_body<KC, 1>(V, S, w, n, wf, re, im);
     double a[P];
 #pragma unroll
     for (int k = 0; k < P / 2; ++k) {
@@ -346,24 +346,27 @@ __global__ __launch_bounds__(1024) void k_multidot_final(const double* partial, 
 
 // w -= sum_k c_k V_k; then, per block, partial sums of either the new
 // projections conj(V_k) w (mode 1, 2 KC reals per block) or |w|^2 (mode 2,
-// one real per block); mode 0 only subtracts.  The coefficients c come from
+// one real per block).  The coefficients c come from
 // the Lanczos state, or, with pin != nullptr, every block totals them from
 // the previous pass's nbin block partials itself (the same sums in every
 // block) and block 0 records them in the state (alpha_index as in
 // lz_record_projection); pin must not alias partial.
 template <int MODE, int KC, int W>
-__device__ inline void sub_fused_body(const double* V, double* w, int64_t n, const double* c, double (&pr)[KC],
-                                      double (&pi)[KC], double& nrm) {
+__device__ inline void sub_fused_body(const double* V, int64_t S, double* w, int64_t n, const double* c,
+                                      double (&pr)[KC], double (&pi)[KC], double& nrm) {
     // W consecutive elements per thread and step (16-byte loads for W = 2)
     typedef double dv __attribute__((ext_vector_type(W)));
     const int64_t nw = n / W;
+    // slot and plane strides: chunked basis (S > 0) or planar vectors (S == 0)
+    const int64_t ks = S ? 2 * KCH : 2 * n, ps = S ? KCH : n;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nw; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = q * W;
+        const double* Vi = V + (S ? kch_ofs(i, S) : i);
         dv vr[KC], vi[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            vr[k] = *(const dv*)(V + 2 * n * k + i);
-            vi[k] = *(const dv*)(V + 2 * n * k + n + i);
+            vr[k] = *(const dv*)(Vi + ks * k);
+            vi[k] = *(const dv*)(Vi + ks * k + ps);
         }
         dv wr = *(const dv*)(w + i), wi = *(const dv*)(w + i + n);
 #pragma unroll
@@ -393,7 +396,7 @@ __device__ inline void sub_fused_body(const double* V, double* w, int64_t n, con
 }
 
 template <int MODE, int KC>
-__global__ __launch_bounds__(256) void k_sub_fused(const double* V, double* w, int64_t n, double* partial,
+__global__ __launch_bounds__(256) void k_sub_fused(const double* V, int64_t S, double* w, int64_t n, double* partial,
                                                    LanczosDev* lz, const double* pin, int nbin, int alpha_index) {
     if (lz->done) return;
     constexpr int P = pow2_pairs(KC);
@@ -412,9 +415,9 @@ __global__ __launch_bounds__(256) void k_sub_fused(const double* V, double* w, i
 #pragma unroll
     for (int k = 0; k < KC; ++k) pr[k] = pi[k] = 0;
     if (n % 2 == 0 && (((uintptr_t)V | (uintptr_t)w) & 15) == 0)
-        sub_fused_body<MODE, KC, 2>(V, w, n, c, pr, pi, nrm);
+        sub_fused_body<MODE, KC, 2>(V, S, w, n, c, pr, pi, nrm);
     else
-        sub_fused_body<MODE, KC, 1>(V, w, n, c, pr, pi, nrm);
+        sub_fused_body<MODE, KC, 1>(V, S, w, n, c, pr, pi, nrm);
     if (MODE == 1) {
         double a[P];
 #pragma unroll
@@ -938,7 +941,19 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
     }
 }
 
-__global__ void k_lz_combine(const double* V, int64_t n, double* out, const LanczosDev* lz) {
+// out[k][plane][n] = slot k of the chunked basis V, k < slots (planar copy)
+__global__ void k_unchunk(const double* V, int64_t S, int64_t n, int slots, double* out, const int* skip) {
+    if (skip && *skip) return;
+    const int64_t total = 2 * n * slots;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / (2 * n), r = e - k * 2 * n;
+        out[e] = V[2 * KCH * k + kch_elem(r, n, S)];
+    }
+}
+
+// out = beta0 sum_k y_k v_k; V planar (S == 0, slot stride 2 n) or chunked
+__global__ void k_lz_combine(const double* V, int64_t S, int64_t n, double* out, const LanczosDev* lz) {
     if (lz->zero) return;
     __shared__ double y[2 * KRYLOV_MAX];
     const int m = lz->m_eff;
@@ -950,9 +965,11 @@ __global__ void k_lz_combine(const double* V, int64_t n, double* out, const Lanc
              q += (int64_t)gridDim.x * blockDim.x) {
             const int64_t i = 2 * q;
             d2 re = {0, 0}, im = {0, 0};
+            const double* Vi = V + (S ? kch_ofs(i, S) : i);
+            const int64_t ks = S ? 2 * KCH : 2 * n, ps = S ? KCH : n;
             for (int k = 0; k < m; ++k) {
-                const double* v = V + 2 * n * k;
-                const d2 vr = *(const d2*)(v + i), vi = *(const d2*)(v + i + n);
+                const double* v = Vi + ks * k;
+                const d2 vr = *(const d2*)v, vi = *(const d2*)(v + ps);
                 re += y[2 * k] * vr - y[2 * k + 1] * vi;
                 im += y[2 * k] * vi + y[2 * k + 1] * vr;
             }
@@ -964,9 +981,11 @@ __global__ void k_lz_combine(const double* V, int64_t n, double* out, const Lanc
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double re = 0, im = 0;
+        const double* Vi = V + (S ? kch_ofs(i, S) : i);
+        const int64_t ks = S ? 2 * KCH : 2 * n, ps = S ? KCH : n;
         for (int k = 0; k < m; ++k) {
-            const double* v = V + 2 * n * k;
-            const double vr = v[i], vi = v[i + n];
+            const double* v = Vi + ks * k;
+            const double vr = v[0], vi = v[ps];
             re += y[2 * k] * vr - y[2 * k + 1] * vi;
             im += y[2 * k] * vi + y[2 * k + 1] * vr;
         }
@@ -982,20 +1001,13 @@ inline int grid_for(int64_t n) {
 
 }  // namespace
 
-void vec_norm2(const double* x, int64_t n, double* partial, int nb, double* out_sum, const int* skip,
-               hipStream_t s) {
-    if (g_dry_run) return;
-    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, x, n, partial, skip);
-    hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(64), 0, s, partial, nb, out_sum, skip);
-}
-
-void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* partial, int nb,
+void lz_start(const double* x, int64_t n, double* v0, int64_t S, LanczosDev* lz, double* partial, int nb,
               hipStream_t s, int nonherm, float* v0f) {
     if (g_dry_run) return;
     hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, x, n, partial,
                        (const int*)nullptr);
     hipLaunchKernelGGL(k_lz_begin, dim3(1), dim3(64), 0, s, partial, nb, lz, nonherm);
-    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, x, n, v0, lz, 1, 0, v0f);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, x, n, v0, S, lz, 1, 0, v0f);
 }
 
 // Instantiates a launch for every basis size 1 .. KRYLOV_MAX.
@@ -1023,42 +1035,33 @@ void lz_start(const double* x, int64_t n, double* v0, LanczosDev* lz, double* pa
     } while (0)
 static_assert(KRYLOV_MAX == 16, "TTN_KC_DISPATCH covers basis sizes up to 16");
 
-void lz_project(const double* V, int kcount, const double* w, int64_t n, double* partial, int nb,
+void lz_project(const double* V, int64_t S, int kcount, const double* w, int64_t n, double* partial, int nb,
                 LanczosDev* lz, int alpha_index, hipStream_t s, const float* wf, bool total) {
     if (g_dry_run) return;
 #define TTN_L(KC) \
-    hipLaunchKernelGGL(k_multidot_partial<KC>, dim3(nb), dim3(RED_THREADS), 0, s, V, w, n, partial, lz, wf)
+    hipLaunchKernelGGL(k_multidot_partial<KC>, dim3(nb), dim3(RED_THREADS), 0, s, V, S, w, n, partial, lz, wf)
     TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
     if (total)
         hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(1024), 0, s, partial, nb, kcount, lz, alpha_index);
 }
 
-void lz_subtract(const double* V, int kcount, double* w, int64_t n, LanczosDev* lz, hipStream_t s) {
-    if (g_dry_run) return;
-#define TTN_L(KC)                                                                                              \
-    hipLaunchKernelGGL((k_sub_fused<0, KC>), dim3(grid_for(n)), dim3(256), 0, s, V, w, n, (double*)nullptr, lz, \
-                       (const double*)nullptr, 0, 0)
-    TTN_KC_DISPATCH(kcount, TTN_L);
-#undef TTN_L
-}
-
 // With fuse (nb <= LZ_FUSE_NB) the totals of the first pass are taken inside
 // k_sub_fused<1> from the partials lz_project left at `partial`, and its own
 // partials go to partial + LZ_PARTIAL_HALF.
-void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, double* partial, int nb,
+void lz_subtract_project(const double* V, int64_t S, int kcount, double* w, int64_t n, double* partial, int nb,
                          LanczosDev* lz, hipStream_t s, bool fuse) {
     if (g_dry_run) return;
     if (fuse) {
 #define TTN_L(KC)                                                                                             \
-    hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial + LZ_PARTIAL_HALF, lz, \
+    hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, S, w, n, partial + LZ_PARTIAL_HALF, lz, \
                        (const double*)partial, nb, kcount - 1)
         TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
         return;
     }
 #define TTN_L(KC)                                                                                         \
-    hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz, \
+    hipLaunchKernelGGL((k_sub_fused<1, KC>), dim3(nb), dim3(256), 0, s, V, S, w, n, partial, lz, \
                        (const double*)nullptr, 0, 0)
     TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
@@ -1067,35 +1070,26 @@ void lz_subtract_project(const double* V, int kcount, double* w, int64_t n, doub
 
 // With fuse the second pass's totals are taken inside k_sub_fused<2> from
 // partial + LZ_PARTIAL_HALF, and beta_j inside the scaling kernel.
-void lz_subtract_next(const double* V, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz, int j,
-                      double* partial, int nb, double tol, hipStream_t s, float* vnextf, bool fuse) {
+void lz_subtract_next(const double* V, int64_t S, int kcount, double* w, int64_t n, double* vnext, LanczosDev* lz,
+                      int j, double* partial, int nb, double tol, hipStream_t s, float* vnextf, bool fuse) {
     if (g_dry_run) return;
     if (fuse) {
 #define TTN_L(KC)                                                                                              \
-    hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz,                  \
+    hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, S, w, n, partial, lz,               \
                        (const double*)(partial + LZ_PARTIAL_HALF), nb, -1)
         TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
-        hipLaunchKernelGGL(k_scale_next, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz,
+        hipLaunchKernelGGL(k_scale_next, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, S, lz,
                            (const double*)partial, nb, j, tol, vnextf);
         return;
     }
 #define TTN_L(KC)                                                                                         \
-    hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, w, n, partial, lz, \
+    hipLaunchKernelGGL((k_sub_fused<2, KC>), dim3(nb), dim3(256), 0, s, V, S, w, n, partial, lz, \
                        (const double*)nullptr, 0, 0)
     TTN_KC_DISPATCH(kcount, TTN_L);
 #undef TTN_L
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(256), 0, s, partial, nb, lz, j, tol);
-    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j, vnextf);
-}
-
-void lz_next(double* w, int64_t n, double* vnext, LanczosDev* lz, int j, double* partial, int nb,
-             double tol, hipStream_t s) {
-    if (g_dry_run) return;
-    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(RED_THREADS), 0, s, w, n, partial, &lz->done);
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(256), 0, s, partial, nb, lz, j, tol);
-    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, lz, 0, j,
-                       (float*)nullptr);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(2 * n)), dim3(256), 0, s, w, n, vnext, S, lz, 0, j, vnextf);
 }
 
 void lz_iter_small(double* V, int j, int m, double* w, int64_t n, LanczosDev* lz, double tol, hipStream_t s) {
@@ -1124,9 +1118,14 @@ void small_evolve(const double* L, const double* R, const double* B, const doubl
                        tol, nonherm ? 1 : 0, x, st);
 }
 
-void lz_combine(const double* V, int64_t n, double* out, LanczosDev* lz, hipStream_t s) {
+void lz_combine(const double* V, int64_t S, int64_t n, double* out, LanczosDev* lz, hipStream_t s) {
     if (g_dry_run) return;
-    hipLaunchKernelGGL(k_lz_combine, dim3(grid_for(n)), dim3(256), 0, s, V, n, out, lz);
+    hipLaunchKernelGGL(k_lz_combine, dim3(grid_for(n)), dim3(256), 0, s, V, S, n, out, lz);
+}
+
+void krylov_unchunk(const double* V, int64_t S, int64_t n, int slots, double* out, const int* skip, hipStream_t s) {
+    if (g_dry_run) return;
+    hipLaunchKernelGGL(k_unchunk, dim3(grid_for(2 * n * slots)), dim3(256), 0, s, V, S, n, slots, out, skip);
 }
 
 // ---------------------------------------------------------------------------
