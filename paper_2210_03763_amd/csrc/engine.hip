@@ -95,6 +95,9 @@ struct ttn_handle {
     float *Xf = nullptr, *Yf = nullptr;
     double *Bstk = nullptr, *Astk = nullptr;
     float *Lf = nullptr, *Rf = nullptr, *Bf = nullptr, *Wf = nullptr, *Ef = nullptr;
+    // FP32 stacks of the fused-left matvec: [N_i (S_L), H_L] and
+    // [H_P, W_i (S_L), identity, W_j (S_R)]
+    float *Lf2 = nullptr, *Wf2 = nullptr;
     double *G = nullptr, *Linv = nullptr, *R1 = nullptr, *R2 = nullptr, *Rq = nullptr, *Cb = nullptr,
            *cholwork = nullptr;
     double* red = nullptr;
@@ -264,7 +267,8 @@ void plan(ttn_handle* h, Bump& b) {
     for (int v = 0; v < nn; ++v) {
         const int64_t n = nsize(h, v);
         h->nmax = std::max(h->nmax, n);
-        h->stack_max = std::max(h->stack_max, (int64_t)(1 + h->scount[v]) * n);
+        // matvec stack [X, U_i (S_L), H_L X, Z_j (S_R)]
+        h->stack_max = std::max(h->stack_max, (int64_t)(2 + h->scount[v]) * n);
         h->Dmax = std::max({h->Dmax, h->DL[v], h->DR[v], h->DP[v]});
         h->max_sites = std::max(h->max_sites, h->scount[v]);
         h->T[v] = b.take<double>(2 * n);
@@ -280,7 +284,7 @@ void plan(ttn_handle* h, Bump& b) {
     }
     // bond stacks (sites below v, size DP^2) are bounded by stack_max as well
     for (int v = 0; v < nn; ++v)
-        h->stack_max = std::max(h->stack_max, (int64_t)(1 + h->scount[v]) * h->DP[v] * h->DP[v]);
+        h->stack_max = std::max(h->stack_max, (int64_t)(2 + h->scount[v]) * h->DP[v] * h->DP[v]);
     // two-site: merged tensors of every edge, their matvec stacks
     // [X, U_i, Z_j, V_k] and the split factors
     h->n2max = h->ngmax = h->mkmax = 0;
@@ -321,6 +325,8 @@ void plan(ttn_handle* h, Bump& b) {
         h->Rf = b.take<float>(2 * smax * D2);
         h->Bf = b.take<float>(2 * smax * D2);
         h->Wf = b.take<float>(2 * smax * D2);
+        h->Lf2 = b.take<float>(2 * smax * D2);
+        h->Wf2 = b.take<float>(2 * (smax + 1) * D2);
         h->Ef = b.take<float>(2 * h->env_max);
     }
     h->Bstk = b.take<double>(2 * smax * D2);
@@ -372,6 +378,7 @@ template <typename R>
 struct Ctx {
     ttn_handle* h;
     const int* skip;
+    double flops_less = 0;   // flops of the next launches that are not algorithmic (padding terms)
     void run(const Gemm<R>& g) {
         char why[256];
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -385,7 +392,7 @@ struct Ctx {
                 e0 = h->ev_pool[idx];
                 e1 = h->ev_pool[idx + 1];
             }
-            const double fl = 8.0 * g.M * g.N * (double)g.Kin * g.Kout * (double)g.B1 * g.B2;
+            const double fl = 8.0 * g.M * g.N * (double)g.Kin * g.Kout * (double)g.B1 * g.B2 - flops_less;
             h->prof_recs.push_back({idx, sizeof(R) == 4 ? 1 : 0, fl, h->in_heff, 0, 0,
                                     h->in_heff ? (int)h->prof_matvecs - 1 : -1});
         }
@@ -851,11 +858,47 @@ void stage_f32(ttn_handle* h, const OpDesc& o, const int* skip) {
         chk(h, o.Wb, 2 * (1 + o.sL + o.sR) * P2, "W stack");
         chk(h, h->Wf, (1 + o.sL + o.sR) * P2, "W stack fp32");
     }
+    const int64_t wl = 2 * (1 + o.sL) * P2;   // [H_P, W_i (S_L)]
+    if (o.Wb) {
+        chk(h, h->Lf2, (1 + o.sL) * L2, "fused-left L stack fp32");
+        chk(h, h->Wf2, (2 + o.sL + o.sR) * P2, "fused-left W stack fp32");
+    }
     convert_d2f_many({{o.Lb, h->Lf, 2 * (1 + o.sL) * L2},
                       {o.Rb, h->Rf, 2 * (1 + o.sR) * R2},
                       {o.Bb, h->Bf, 2 * (1 + o.sL) * R2},
-                      {o.Wb, h->Wf, 2 * (1 + o.sL + o.sR) * P2}},
+                      {o.Wb, h->Wf, 2 * (1 + o.sL + o.sR) * P2},
+                      // the fused-left matvec's stacks (nodes below the root)
+                      {o.Wb ? o.Lb + 2 * L2 : nullptr, h->Lf2, 2 * o.sL * L2},
+                      {o.Wb ? o.Lb : nullptr, h->Lf2 + 2 * o.sL * L2, 2 * L2},
+                      {o.Wb, h->Wf2, wl},
+                      {nullptr, h->Wf2 + wl, 2 * P2, o.Wb ? o.DP : 0},
+                      {o.Wb ? o.Wb + wl : nullptr, h->Wf2 + wl + 2 * P2, 2 * o.sR * P2}},
                      skip, h->stream);
+}
+
+// Y = H X for operators with a parent leg (FP32 stacks from stage_f32), in
+// four launches instead of five: the left block Hamiltonian rides with the
+// left-site operators (stack [N_i, H_L], outputs [U_i, T = H_L X] in slots
+// 1 .. 1 + sL) and T enters the parent-leg sum through an identity operator
+// (stack [H_P, W_i, I, W_j] over [X, U_i, T, Z_j]).  The identity term costs
+// D_P more rows of K in the parent-leg GEMM and saves a launch (with its
+// split-K reduction) per matvec; its flops are left out of the algorithmic
+// count.
+void apply_op_fused_left(Ctx<float>& c, const OpDesc& o, const float* Lf2, const float* Rf, const float* Bf,
+                         const float* Wf2, float* Xs, float* Y) {
+    const int DL = o.DL, DR = o.DR, DP = o.DP, sL = o.sL, sR = o.sR;
+    const int64_t n = (int64_t)DL * DR * DP, sx = 2 * n;
+    const int64_t L2 = (int64_t)DL * DL, R2 = (int64_t)DR * DR, P2 = (int64_t)DP * DP;
+    // stage A: U_i = N_i X and T = H_L X on the left leg
+    leg_apply<float>(c, 0, Lf2, 2 * L2, Xs, 0, Xs + sx, sx, DL, DR, DP, 1 + sL, 0);
+    // stage B: Z_j = N_j X on the right leg, after T
+    if (sR > 0) leg_apply<float>(c, 1, Rf + 2 * R2, 2 * R2, Xs, 0, Xs + sx * (2 + sL), sx, DL, DR, DP, sR, 0);
+    // stage C: Y = H_R X + sum_i A_i U_i on the right leg
+    if (Bf) leg_apply_sum<float>(c, 1, Bf, 2 * R2, Xs, sx, Y, DL, DR, DP, 1 + sL, 0);
+    // stage D: Y (+)= H_P X + sum_i W_i U_i + T + sum_j W_j Z_j on the parent leg
+    c.flops_less = 8.0 * (double)n * DP;
+    leg_apply_sum<float>(c, 2, Wf2, 2 * P2, Xs, sx, Y, DL, DR, DP, 2 + sL + sR, Bf ? 1 : 0);
+    c.flops_less = 0;
 }
 
 // staged: the mixed-precision matvec whose input is already in the FP32 slot
@@ -911,8 +954,11 @@ void apply_op_prec(ttn_handle* h, const OpDesc& o, const double* x, double* y, c
         }
         {
             HeffMark mark(h);
-            apply_op<float>(c, o, h->Lf, o.Rb ? h->Rf : nullptr, o.Bb ? h->Bf : nullptr,
-                            o.Wb ? h->Wf : nullptr, h->Xf, h->Yf);
+            if (o.Wb)
+                apply_op_fused_left(c, o, h->Lf2, h->Rf, o.Bb ? h->Bf : nullptr, h->Wf2, h->Xf, h->Yf);
+            else
+                apply_op<float>(c, o, h->Lf, o.Rb ? h->Rf : nullptr, o.Bb ? h->Bf : nullptr, nullptr, h->Xf,
+                                h->Yf);
         }
         if (!staged) convert_f2d(h->Yf, y, 2 * n, skip, h->stream);
     } else {

@@ -1151,7 +1151,8 @@ __global__ void k_d2f_batch(D2FBatch b, int64_t total, const int* skip) {
             off -= b.c[k];
             ++k;
         }
-        b.y[k][off] = (float)b.x[k][off];
+        const int D = b.eye[k];
+        b.y[k][off] = D ? ((off < (int64_t)D * D && off % (D + 1) == 0) ? 1.0f : 0.0f) : (float)b.x[k][off];
     }
 }
 __global__ void k_f2d(const float* x, double* y, int64_t c, const int* skip) {
@@ -1229,7 +1230,7 @@ void convert_d2f_many(std::initializer_list<D2FItem> items, const int* skip, hip
     D2FBatch b{};
     int64_t total = 0;
     for (const D2FItem& it : items) {
-        if (!it.x || it.count <= 0) continue;
+        if ((!it.x && it.eye <= 0) || it.count <= 0) continue;
         if (b.n == D2F_MAX) {   // full: flush
             hipLaunchKernelGGL(k_d2f_batch, dim3(grid_for(total)), dim3(256), 0, s, b, total, skip);
             b = D2FBatch{};
@@ -1238,6 +1239,7 @@ void convert_d2f_many(std::initializer_list<D2FItem> items, const int* skip, hip
         b.x[b.n] = it.x;
         b.y[b.n] = it.y;
         b.c[b.n] = it.count;
+        b.eye[b.n] = it.eye > 0 ? it.eye : 0;
         ++b.n;
         total += it.count;
     }

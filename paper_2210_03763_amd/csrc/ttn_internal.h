@@ -163,17 +163,21 @@ void lz_combine(const double* V, int64_t S, int64_t n, double* out, LanczosDev* 
 
 // conversions and copies
 void convert_d2f(const double* x, float* y, int64_t count, const int* skip, hipStream_t s);
-// several FP64 -> FP32 conversions in one launch (null or empty items skipped)
+// several FP64 -> FP32 conversions in one launch (null or empty items
+// skipped); an item with eye = D > 0 writes the planar D x D identity
+// (count 2 D^2) instead of converting x
 struct D2FItem {
     const double* x;
     float* y;
     int64_t count;
+    int eye = 0;
 };
-constexpr int D2F_MAX = 6;
+constexpr int D2F_MAX = 10;
 struct D2FBatch {
     const double* x[D2F_MAX];
     float* y[D2F_MAX];
     int64_t c[D2F_MAX];
+    int eye[D2F_MAX];
     int n;
 };
 void convert_d2f_many(std::initializer_list<D2FItem> items, const int* skip, hipStream_t s);
