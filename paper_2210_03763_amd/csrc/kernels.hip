@@ -1844,36 +1844,46 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
         }
     __threadfence_block();
     __syncthreads();
-    // inverse by block diagonals: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ; the
-    // diagonal slots of L are free now and hold each wave's intermediate T
-    for (int dl = 1; dl < NB; ++dl) {
-        const int J = wave, I = J + dl;
-        if (I < NB) {
-            const int m = lane & 15, q = lane >> 4;
-            // B fragments X_KJ[kk + q][m] of every K of this level, then A = L_IK
-            double xb_r[4 * (CB_MAXNB - 1)], xb_i[4 * (CB_MAXNB - 1)];
+    // inverse by block columns: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ for
+    // I = J + 1 ..; each wave owns one column J (columns 0-3 on waves 0-3 and
+    // 7-4 on waves 4-7, so that the two waves sharing a SIMD share the work
+    // evenly) and keeps the column's blocks X_KJ as B fragments in registers
+    // (the output layout of one product is the B fragment layout of the
+    // next), so the waves need no barrier between blocks; only the diagonal
+    // inverses X_II, written before the last barrier, come from memory
+    static_assert(CB_WAVES == 8 && CB_MAXNB == 8, "one wave per block column");
+    {
+        const int J = wave < 4 ? wave : 11 - wave;
+        const int m = lane & 15, q = lane >> 4;
+        double xb_r[4 * CB_MAXNB], xb_i[4 * CB_MAXNB];   // X_{J+t, J}, fragment j of block t
 #pragma unroll
-            for (int t = 0; t < CB_MAXNB - 1; ++t)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int K = J + t;
-                    const bool ok = t < dl;
-                    const int64_t g = ok ? (CB * K + 4 * j + q) + (int64_t)Dp * (CB * J + m) : 0;
-                    xb_r[4 * t + j] = ok ? Xr[g] : 0.0;
-                    xb_i[4 * t + j] = ok ? Xi[g] : 0.0;
-                }
-            double xa_r[4], xa_i[4];   // A fragments of X_II[m][kk + q]
+        for (int j = 0; j < 4 * CB_MAXNB; ++j) {
+            xb_r[j] = 0.0;
+            xb_i[j] = 0.0;
+        }
+        if (J < NB) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int64_t g = (CB * I + m) + (int64_t)Dp * (CB * I + 4 * j + q);
-                xa_r[j] = Xr[g];
-                xa_i[j] = Xi[g];
+                const int64_t g = (CB * J + 4 * j + q) + (int64_t)Dp * (CB * J + m);
+                xb_r[j] = Xr[g];
+                xb_i[j] = Xi[g];
             }
-            // four independent accumulator chains (T = tr + ur, ti + ui)
-            cb_d4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0}, ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+        }
 #pragma unroll
-            for (int t = 0; t < CB_MAXNB - 1; ++t) {
-                if (t < dl) {
+        for (int dl = 1; dl < CB_MAXNB; ++dl) {
+            const int I = J + dl;
+            if (I < NB) {
+                double xa_r[4], xa_i[4];   // A fragments of X_II[m][kk + q]
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t g = (CB * I + m) + (int64_t)Dp * (CB * I + 4 * j + q);
+                    xa_r[j] = Xr[g];
+                    xa_i[j] = Xi[g];
+                }
+                // four independent accumulator chains (T = tr + ur, ti + ui)
+                cb_d4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0}, ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < dl; ++t) {
                     const double* Lr = s_re + 256 * cb_bidx(I, J + t);
                     const double* Li = s_im + 256 * cb_bidx(I, J + t);
 #pragma unroll
@@ -1886,30 +1896,32 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                         ui = cb_mfma(li, br, ui);
                     }
                 }
-            }
-            tr += ur;
-            ti += ui;
-            // X_IJ = - X_II T: the output layout of T is the B fragment layout
-            cb_d4 orr = {0, 0, 0, 0}, oi = {0, 0, 0, 0}, o2r = {0, 0, 0, 0}, o2i = {0, 0, 0, 0};
+                tr += ur;
+                ti += ui;
+                // X_IJ = - X_II T
+                cb_d4 orr = {0, 0, 0, 0}, oi = {0, 0, 0, 0}, o2r = {0, 0, 0, 0}, o2i = {0, 0, 0, 0};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                orr = cb_mfma(-xa_r[j], tr[j], orr);
-                oi = cb_mfma(-xa_r[j], ti[j], oi);
-                o2r = cb_mfma(xa_i[j], ti[j], o2r);
-                o2i = cb_mfma(-xa_i[j], tr[j], o2i);
-            }
-            orr += o2r;
-            oi += o2i;
+                for (int j = 0; j < 4; ++j) {
+                    orr = cb_mfma(-xa_r[j], tr[j], orr);
+                    oi = cb_mfma(-xa_r[j], ti[j], oi);
+                    o2r = cb_mfma(xa_i[j], ti[j], o2r);
+                    o2i = cb_mfma(-xa_i[j], tr[j], o2i);
+                }
+                orr += o2r;
+                oi += o2i;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t g = (CB * I + q + 4 * r) + (int64_t)Dp * (CB * J + m);
-                Xr[g] = orr[r];
-                Xi[g] = oi[r];
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t g = (CB * I + q + 4 * r) + (int64_t)Dp * (CB * J + m);
+                    Xr[g] = orr[r];
+                    Xi[g] = oi[r];
+                    xb_r[4 * dl + r] = orr[r];
+                    xb_i[4 * dl + r] = oi[r];
+                }
             }
         }
-        __threadfence_block();
-        __syncthreads();
     }
+    __threadfence_block();
+    __syncthreads();
     if (!direct)
         for (int j = wave; j < D; j += CB_WAVES)
             for (int i = lane; i < D; i += 64) {
