@@ -675,138 +675,121 @@ __global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
 // Replaces about a hundred launches per evolution of the bottom nodes and
 // their bonds.
 // ---------------------------------------------------------------------------
-constexpr int SMALL_THREADS = 256;
+constexpr int SMALL_THREADS = 1024;
 
-// Elements owned by a thread of the fused kernel: i = threadIdx.x +
-// SMALL_THREADS t, t < SMALL_PER (n <= SMALL_EVOLVE_N), with their (l, r, p)
-// split computed once per launch.  Every element-wise pass of the kernel uses
-// this ownership, so the only barriers are those that publish a whole vector
-// (the matvec input and the left/right images) or a reduction.
-constexpr int SMALL_PER = (int)(SMALL_EVOLVE_N / SMALL_THREADS);
-static_assert(SMALL_PER * SMALL_THREADS == SMALL_EVOLVE_N, "elements must split evenly over the threads");
-struct SmallIdx {
-    int l[SMALL_PER], r[SMALL_PER], p[SMALL_PER];
-};
+// Two ownerships of the elements i < n <= SMALL_EVOLVE_N.  In the matvec a
+// quad of adjacent lanes shares the elements i = threadIdx.x / 4 +
+// SMALL_GROUPS t, t < SMALL_PER, and the four lanes split the terms of each
+// element (images and operator stacks dealt round-robin), summed by two lane
+// exchanges; the (l, r, p) split of every element is tabulated in LDS once
+// per launch (10 bits each).  The projections give wave k Krylov vector k;
+// the subtractions, norms and scaling give thread i element i.
+constexpr int SMALL_SPLIT = 4;
+constexpr int SMALL_GROUPS = SMALL_THREADS / SMALL_SPLIT;
+constexpr int SMALL_PER = (int)(SMALL_EVOLVE_N / SMALL_GROUPS);
+static_assert(SMALL_PER * SMALL_GROUPS == SMALL_EVOLVE_N, "elements must split evenly over the quads");
+static_assert(SMALL_EVOLVE_N == SMALL_THREADS, "one element per thread in the vector passes");
+static_assert(SMALL_EVOLVE_N <= 1024, "leg dimensions must fit the 10-bit fields of the index table");
+
+// acc += sum_q op[o + D q] src[base + sq q], q < D (complex, planar op of D^2
+// entries and src of n entries)
+__device__ inline void small_term(const double* op, int D, int o, const double* src, int n, int base, int sq,
+                                  double& ar, double& ai) {
+    const int D2 = D * D;
+#pragma unroll 4
+    for (int q = 0; q < D; ++q) {
+        const double orr = op[o + D * q], oi = op[D2 + o + D * q];
+        const double xr = src[base + sq * q], xi = src[n + base + sq * q];
+        ar += orr * xr - oi * xi;
+        ai += orr * xi + oi * xr;
+    }
+}
 
 // y = Op x; S holds the left (U_k = L_k x_L x, k = 1..sL) and right (Z_j =
-// R_j x_R x) images, slot stride 2n.  y is written only at the calling
-// thread's own elements (no closing barrier).
+// R_j x_R x) images, slot stride 2n.  Ends with a barrier (y is complete).
 __device__ void small_matvec(const double* L, const double* Rr, const double* B, const double* W, int DL, int DR,
-                             int DP, int sL, int sR, const SmallIdx& ix, const double* x, double* S, double* y) {
+                             int DP, int sL, int sR, const int* sidx, const double* x, double* S, double* y) {
     const int n = DL * DR * DP;
-    const int L2 = DL * DL, R2 = DR * DR, P2 = DP * DP;
     const int nz = (W && sR > 0) ? sR : 0;
-    for (int k = 0; k < sL + nz; ++k) {
+    const int q = threadIdx.x & (SMALL_SPLIT - 1), g = threadIdx.x / SMALL_SPLIT;
+    // images: lane q of a quad forms images k = q, q + 4, ... of its elements
+    for (int k = q; k < sL + nz; k += SMALL_SPLIT) {
         const bool left = k < sL;
-        const double* op = left ? L + 2 * L2 * (k + 1) : Rr + 2 * R2 * (k - sL + 1);
-#pragma unroll
+#pragma unroll 1
         for (int t = 0; t < SMALL_PER; ++t) {
-            const int i = threadIdx.x + SMALL_THREADS * t;
+            const int i = g + SMALL_GROUPS * t;
             if (i < n) {
-                const int l = ix.l[t], r = ix.r[t], p = ix.p[t];
+                const int lx = sidx[i] & 1023, rx = (sidx[i] >> 10) & 1023;
                 double ar = 0, ai = 0;
-                if (left) {
-#pragma unroll 4
-                    for (int q = 0; q < DL; ++q) {
-                        const double orr = op[l + DL * q], oi = op[L2 + l + DL * q];
-                        const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
-                        ar += orr * xr - oi * xi;
-                        ai += orr * xi + oi * xr;
-                    }
-                } else {
-#pragma unroll 4
-                    for (int q = 0; q < DR; ++q) {
-                        const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
-                        const double xr = x[l + DL * (q + DR * p)], xi = x[n + l + DL * (q + DR * p)];
-                        ar += orr * xr - oi * xi;
-                        ai += orr * xi + oi * xr;
-                    }
-                }
+                if (left)
+                    small_term(L + 2 * DL * DL * (k + 1), DL, lx, x, n, i - lx, 1, ar, ai);
+                else
+                    small_term(Rr + 2 * DR * DR * (k - sL + 1), DR, rx, x, n, i - DL * rx, DL, ar, ai);
                 S[2 * n * k + i] = ar;
                 S[2 * n * k + n + i] = ai;
             }
         }
     }
     __syncthreads();
-#pragma unroll
+    // sums: unit 0 is the left block Hamiltonian, units 1..sL+1 the right-leg
+    // stack (H_R x, A_i U_i), the next sL+nz+1 the parent-leg stack (H_P x,
+    // W U, W Z); lane q takes the units u = q mod 4
+    const int uW = 1 + (B ? sL + 1 : 0);
+#pragma unroll 1
     for (int t = 0; t < SMALL_PER; ++t) {
-        const int i = threadIdx.x + SMALL_THREADS * t;
-        if (i >= n) continue;
-        const int l = ix.l[t], r = ix.r[t], p = ix.p[t];
+        const int i = g + SMALL_GROUPS * t;
         double ar = 0, ai = 0;
-#pragma unroll 4
-        for (int q = 0; q < DL; ++q) {   // block Hamiltonian of the left leg
-            const double orr = L[l + DL * q], oi = L[L2 + l + DL * q];
-            const double xr = x[q + DL * (r + DR * p)], xi = x[n + q + DL * (r + DR * p)];
-            ar += orr * xr - oi * xi;
-            ai += orr * xi + oi * xr;
+        if (i < n) {
+            const int e = sidx[i];
+            const int l = e & 1023, r = (e >> 10) & 1023, p = e >> 20;
+            if (q == 0) small_term(L, DL, l, x, n, i - l, 1, ar, ai);
+            if (B)
+                for (int k = (q - 1) & (SMALL_SPLIT - 1); k <= sL; k += SMALL_SPLIT)
+                    small_term(B + 2 * DR * DR * k, DR, r, k == 0 ? x : S + 2 * n * (k - 1), n, i - DL * r, DL,
+                               ar, ai);
+            if (W)
+                for (int k = (q - uW) & (SMALL_SPLIT - 1); k <= sL + nz; k += SMALL_SPLIT)
+                    small_term(W + 2 * DP * DP * k, DP, p, k == 0 ? x : S + 2 * n * (k - 1), n,
+                               i - DL * DR * p, DL * DR, ar, ai);
         }
-        if (B)
-            for (int k = 0; k <= sL; ++k) {   // right leg: H_R x + sum_i A_i U_i
-                const double* op = B + 2 * R2 * k;
-                const double* src = k == 0 ? x : S + 2 * n * (k - 1);
-#pragma unroll 4
-                for (int q = 0; q < DR; ++q) {
-                    const double orr = op[r + DR * q], oi = op[R2 + r + DR * q];
-                    const double xr = src[l + DL * (q + DR * p)], xi = src[n + l + DL * (q + DR * p)];
-                    ar += orr * xr - oi * xi;
-                    ai += orr * xi + oi * xr;
-                }
-            }
-        if (W)
-            for (int k = 0; k <= sL + nz; ++k) {   // parent leg: H_P x + sum W U + sum W Z
-                const double* op = W + 2 * P2 * k;
-                const double* src = k == 0 ? x : S + 2 * n * (k - 1);
-#pragma unroll 4
-                for (int q = 0; q < DP; ++q) {
-                    const double orr = op[p + DP * q], oi = op[P2 + p + DP * q];
-                    const double xr = src[l + DL * (r + DR * q)], xi = src[n + l + DL * (r + DR * q)];
-                    ar += orr * xr - oi * xi;
-                    ai += orr * xi + oi * xr;
-                }
-            }
-        y[i] = ar;
-        y[n + i] = ai;
+        // every lane of the quad shares i, so all four take part
+        ar += __shfl_xor(ar, 1, 64);
+        ai += __shfl_xor(ai, 1, 64);
+        ar += __shfl_xor(ar, 2, 64);
+        ai += __shfl_xor(ai, 2, 64);
+        if (q == 0 && i < n) {
+            y[i] = ar;
+            y[n + i] = ai;
+        }
     }
-}
-
-// c_k = <v_k, w> for k < kc (planar vectors of n in LDS) over the calling
-// thread's own elements, summed over the block with P = the smallest power
-// of two >= 2 kc values; the totals land in c[2 kc] (LDS) behind one barrier.
-template <int P>
-__device__ void small_project_p(const double* V, int kc, const double* w, int n, double* c, double* sh) {
-    double a[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) a[k] = 0.0;
-#pragma unroll
-    for (int t = 0; t < SMALL_PER; ++t) {
-        const int i = threadIdx.x + SMALL_THREADS * t;
-        if (i >= n) continue;
-        const double wr = w[i], wi = w[n + i];
-#pragma unroll
-        for (int k = 0; k < P / 2; ++k)
-            if (k < kc) {
-                const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
-                a[2 * k] += vr * wr + vi * wi;
-                a[2 * k + 1] += vr * wi - vi * wr;
-            }
-    }
-    const double tot = block_sum_p<P>(a, sh);
-    if (threadIdx.x < 2 * kc) c[threadIdx.x] = tot;
     __syncthreads();
 }
 
-__device__ void small_project(const double* V, int kc, const double* w, int n, double* c, double* sh) {
-    if (kc <= 1)
-        small_project_p<2>(V, kc, w, n, c, sh);
-    else if (kc <= 2)
-        small_project_p<4>(V, kc, w, n, c, sh);
-    else if (kc <= 4)
-        small_project_p<8>(V, kc, w, n, c, sh);
-    else if (kc <= 8)
-        small_project_p<16>(V, kc, w, n, c, sh);
-    else
-        small_project_p<32>(V, kc, w, n, c, sh);
+// c_k = <v_k, w> for k < kc (planar vectors of n in LDS, w complete on
+// entry): wave k forms product k over all n elements and reduces it across
+// its lanes; the totals land in c[2 kc] (LDS) behind one barrier.
+static_assert(KRYLOV_MAX <= SMALL_THREADS / 64, "one wave per Krylov vector in the projections");
+__device__ void small_project(const double* V, int kc, const double* w, int n, double* c) {
+    const int lane = threadIdx.x & 63, k = threadIdx.x >> 6;
+    if (k < kc) {
+        const double* v = V + 2 * n * k;
+        double re = 0, im = 0;
+        for (int i = lane; i < n; i += 64) {
+            const double vr = v[i], vi = v[n + i], wr = w[i], wi = w[n + i];
+            re += vr * wr + vi * wi;
+            im += vr * wi - vi * wr;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            re += __shfl_xor(re, o, 64);
+            im += __shfl_xor(im, o, 64);
+        }
+        if (lane == 0) {
+            c[2 * k] = re;
+            c[2 * k + 1] = im;
+        }
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL, const double* gR, const double* gB,
@@ -815,7 +798,8 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
                                                              double* x, StepDev* st) {
     __shared__ double pool[SMALL_EVOLVE_POOL];
     __shared__ LanczosDev lz;
-    __shared__ double sh32[4 * 32];
+    __shared__ double sh2[2 * (SMALL_THREADS / 64)];
+    __shared__ int sidx[SMALL_EVOLVE_N];
     __shared__ double c[32];
     __shared__ double s_beta;
     __shared__ int s_stop;
@@ -837,26 +821,17 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
         for (int e = threadIdx.x; e < 2 * R2 * (1 + sL); e += blockDim.x) B[e] = gB[e];
     if (gW)
         for (int e = threadIdx.x; e < 2 * P2 * (1 + sL + sR); e += blockDim.x) W[e] = gW[e];
-    SmallIdx ix;
-#pragma unroll
-    for (int t = 0; t < SMALL_PER; ++t) {
-        const int i = threadIdx.x + SMALL_THREADS * t;
-        ix.l[t] = i % DL;
-        ix.r[t] = (i / DL) % DR;
-        ix.p[t] = i / (DL * DR);
-    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sidx[i] = (i % DL) | ((i / DL) % DR) << 10 | (i / (DL * DR)) << 20;
+    const int me_i = threadIdx.x;   // this thread's element in the vector passes
     // v_0 = x / ||x||
     double a[2] = {0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < SMALL_PER; ++t) {
-        const int i = threadIdx.x + SMALL_THREADS * t;
-        if (i >= n) continue;
-        const double xr = x[i], xi = x[n + i];
-        w[i] = xr;
-        w[n + i] = xi;
+    if (me_i < n) {
+        const double xr = x[me_i], xi = x[n + me_i];
+        w[me_i] = xr;
+        w[n + me_i] = xi;
         a[0] += xr * xr + xi * xi;
     }
-    double tot = block_sum_p<2>(a, sh32);
+    double tot = block_sum_p<2>(a, sh2);
     if (threadIdx.x == 0) {
         lz.beta0 = sqrt(tot);
         lz.zero = tot == 0.0 ? 1 : 0;
@@ -873,9 +848,9 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
     __syncthreads();
     for (int j = 0; j < m; ++j) {
         const int kc = j + 1;
-        small_matvec(L, nz ? Rr : nullptr, gB ? B : nullptr, gW ? W : nullptr, DL, DR, DP, sL, sR, ix,
+        small_matvec(L, nz ? Rr : nullptr, gB ? B : nullptr, gW ? W : nullptr, DL, DR, DP, sL, sR, sidx,
                      V + 2 * n * j, S, w);
-        small_project(V, kc, w, n, c, sh32);
+        small_project(V, kc, w, n, c);
         if (threadIdx.x == 0) {
             lz.alpha[j] = c[2 * j];
             lz.m_eff = j + 1;
@@ -883,15 +858,14 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
         if (nonherm && threadIdx.x < 2 * kc) lz.hs[2 * j * KRYLOV_MAX + threadIdx.x] = c[threadIdx.x];
         if (j == m - 1) break;
         // w -= V c, second projection, w -= V c' (each thread on its own
-        // elements: the projections' barriers order these passes)
+        // element; the second projection reads all of w, behind a barrier)
         a[0] = 0.0;
         a[1] = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-            for (int t = 0; t < SMALL_PER; ++t) {
-                const int i = threadIdx.x + SMALL_THREADS * t;
-                if (i >= n) continue;
+            if (me_i < n) {
+                const int i = me_i;
                 double wr = w[i], wi = w[n + i];
+#pragma unroll 2
                 for (int k = 0; k < kc; ++k) {
                     const double vr = V[2 * n * k + i], vi = V[2 * n * k + n + i];
                     wr -= c[2 * k] * vr - c[2 * k + 1] * vi;
@@ -902,11 +876,12 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_evolve(const double* gL
                 if (pass == 1) a[0] += wr * wr + wi * wi;
             }
             if (pass == 0) {
-                small_project(V, kc, w, n, c, sh32);
+                __syncthreads();
+                small_project(V, kc, w, n, c);
                 if (nonherm && threadIdx.x < 2 * kc) lz.hs[2 * j * KRYLOV_MAX + threadIdx.x] += c[threadIdx.x];
             }
         }
-        tot = block_sum_p<2>(a, sh32);
+        tot = block_sum_p<2>(a, sh2);
         if (threadIdx.x == 0) {
             const double b = sqrt(tot);
             const double bprev = j > 0 ? lz.beta[j - 1] : 0.0;
