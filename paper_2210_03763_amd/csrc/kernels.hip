@@ -1591,7 +1591,14 @@ __device__ inline void cb_sub_abh_mfma(const double* Ar, const double* Ai, const
 }
 
 // Cholesky of the 16 x 16 Hermitian block (br, bi) in place by one wave:
-// L lower (upper zeroed); dinv[j] = 1 / L_jj to ds[0..15]; cs: 32 doubles.
+// L lower (upper zeroed); dinv[j] = 1 / L_jj to ds[0..15]; cs: 128 doubles.
+// Lane (r, g) holds row r of columns 4 g .. 4 g + 3.  The columns go in four
+// groups of four: the 16 lanes of group g factor its columns in registers
+// (each pivot and each entry L[c][j] the group's later columns need comes by
+// a lane read, no memory round trip), publish the four columns through LDS
+// once, and the lanes of the later groups take the rank-4 update.  Every
+// entry sees its subtractions in the order j = 0, 1, .., as in the
+// column-by-column form.
 __device__ inline void cb_chol_diag(double* br, double* bi, double* ds, double* cs, int lane, int& bad) {
     const int r = lane & 15, cg = lane >> 4;
     double a_r[4], a_i[4];
@@ -1600,36 +1607,64 @@ __device__ inline void cb_chol_diag(double* br, double* bi, double* ds, double* 
         a_r[s] = br[r + CB * (4 * cg + s)];
         a_i[s] = bi[r + CB * (4 * cg + s)];
     }
-    double* cre = cs;
-    double* cim = cs + CB;
+    double* cre = cs;            // [4 columns][16 rows]
+    double* cim = cs + 4 * CB;
 #pragma unroll
-    for (int j = 0; j < CB; ++j) {
-        const int js = j & 3, jg = j >> 2;
-        const double piv = cb_readlane(a_r[js], j + CB * jg);
-        bad |= !(piv > 1e-290);
-        const double pv = piv > 1e-290 ? piv : 1e-290;
-        double y = __builtin_amdgcn_rsq(pv);   // 1/sqrt refined by two Newton steps
-        y = y * (1.5 - 0.5 * pv * y * y);
-        y = y * (1.5 - 0.5 * pv * y * y);
-        if (lane == 0) ds[j] = y;
-        if (cg == jg) {
-            double vr = a_r[js], vi = a_i[js];
-            vr = r > j ? vr * y : (r == j ? pv * y : 0.0);
-            vi = r > j ? vi * y : 0.0;
-            a_r[js] = vr;
-            a_i[js] = vi;
-            cre[r] = vr;
-            cim[r] = vi;
-        }
-        cb_wave_sync();
-        const double lr = cre[r], li = cim[r];
+    for (int G = 0; G < 4; ++G) {
+        const bool mine = cg == G;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int c = 4 * cg + s;
-            if (c > j) {
-                const double cr_ = cre[c], ci_ = cim[c];
-                a_r[s] -= lr * cr_ + li * ci_;
-                a_i[s] -= li * cr_ - lr * ci_;
+            const int j = 4 * G + s;
+            const double piv = cb_readlane(a_r[s], j + CB * G);
+            bad |= !(piv > 1e-290);
+            const double pv = piv > 1e-290 ? piv : 1e-290;
+            double y = __builtin_amdgcn_rsq(pv);   // 1/sqrt refined by two Newton steps
+            y = y * (1.5 - 0.5 * pv * y * y);
+            y = y * (1.5 - 0.5 * pv * y * y);
+            if (lane == 0) ds[j] = y;
+            {
+                const double vr = r > j ? a_r[s] * y : (r == j ? pv * y : 0.0);
+                const double vi = r > j ? a_i[s] * y : 0.0;
+                a_r[s] = mine ? vr : a_r[s];
+                a_i[s] = mine ? vi : a_i[s];
+            }
+            // the group's later columns c: a[r][c] -= L[r][j] conj(L[c][j])
+#pragma unroll
+            for (int t = s + 1; t < 4; ++t) {
+                const int c = 4 * G + t;
+                const double cr_ = cb_readlane(a_r[s], c + CB * G), ci_ = cb_readlane(a_i[s], c + CB * G);
+                const double lr = a_r[s], li = a_i[s];
+                const double ur = a_r[t] - (lr * cr_ + li * ci_);
+                const double ui = a_i[t] - (li * cr_ - lr * ci_);
+                a_r[t] = mine ? ur : a_r[t];
+                a_i[t] = mine ? ui : a_i[t];
+            }
+        }
+        if (G == 3) break;
+        if (mine)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                cre[r + CB * s] = a_r[s];
+                cim[r + CB * s] = a_i[s];
+            }
+        cb_wave_sync();
+        if (cg > G) {
+            // rank-4 update of the later groups' columns c = 4 cg + t
+            double lr[4], li[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                lr[s] = cre[r + CB * s];
+                li[s] = cim[r + CB * s];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int c = 4 * cg + t;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const double cr_ = cre[c + CB * s], ci_ = cim[c + CB * s];
+                    a_r[t] -= lr[s] * cr_ + li[s] * ci_;
+                    a_i[t] -= li[s] * cr_ - lr[s] * ci_;
+                }
             }
         }
         cb_wave_sync();
@@ -1692,6 +1727,7 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                                                          double* work, StepDev* st) {
     __shared__ double s_re[CB_NBLK * 256], s_im[CB_NBLK * 256];
     __shared__ double s_cs[CB_WAVES * 64];
+    __shared__ double s_col[8 * CB];   // the diagonal factorization's four published columns
     __shared__ double s_dinv[CB_MAXNB * CB];
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1742,13 +1778,16 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
     }
     __syncthreads();
     int bad = 0;
-    if (wave == 0) cb_chol_diag(s_re, s_im, dall, csw, lane, bad);
+    if (wave == 0) cb_chol_diag(s_re, s_im, dall, s_col, lane, bad);
     __syncthreads();
     for (int K = 0; K < NB; ++K) {
         const double* Lkr = s_re + 256 * cb_bidx(K, K);
         const double* Lki = s_im + 256 * cb_bidx(K, K);
         const double* dsum = dall + CB * K;
-        // panel: rows of A_IK (I > K) solve L_IK L_KK^H = A_IK by substitution
+        // panel: rows of A_IK (I > K) solve L_IK L_KK^H = A_IK by substitution,
+        // column-oriented: once x_k is known it is taken out of every later
+        // column at once, so the dependent chain is one product per column
+        // (the subtractions of each column still run in the order k = 0, 1, ..)
         const int nrows = CB * (NB - K - 1);
         if (tid < nrows) {
             const int I = K + 1 + tid / CB, r = tid % CB;
@@ -1757,16 +1796,20 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
             double xr[CB], xi[CB];
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                double sr = ar[r + CB * c], si = ai[r + CB * c];
+                xr[c] = ar[r + CB * c];
+                xi[c] = ai[r + CB * c];
+            }
 #pragma unroll
-                for (int k = 0; k < c; ++k) {   // - x_k conj(L[c][k])
+            for (int k = 0; k < CB; ++k) {
+                const double dk = dsum[k];
+                xr[k] *= dk;
+                xi[k] *= dk;
+#pragma unroll
+                for (int c = k + 1; c < CB; ++c) {   // - x_k conj(L[c][k])
                     const double l_r = Lkr[c + CB * k], l_i = -Lki[c + CB * k];
-                    sr -= xr[k] * l_r - xi[k] * l_i;
-                    si -= xr[k] * l_i + xi[k] * l_r;
+                    xr[c] -= xr[k] * l_r - xi[k] * l_i;
+                    xi[c] -= xr[k] * l_i + xi[k] * l_r;
                 }
-                const double dc = dsum[c];
-                xr[c] = sr * dc;
-                xi[c] = si * dc;
             }
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
@@ -1776,18 +1819,22 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
         }
         __syncthreads();
         // trailing update A_IJ -= L_IK L_JK^H (K < J <= I); wave 0 first updates
-        // the next diagonal block and factors it (look-ahead)
+        // the next diagonal block and factors it (look-ahead).  Wave 4, which
+        // shares wave 0's SIMD, takes no update blocks, so the factorization's
+        // serial chain has that SIMD to itself; waves 1-3 and 5-7 share the rest
         const int m = NB - K - 1, nt = m * (m + 1) / 2;
+        constexpr int UPD = CB_WAVES - 2;
+        const int uw = wave < 4 ? wave - 1 : wave - 2;
         if (wave == 0) {
             if (m > 0) {
                 const int b1 = cb_bidx(K + 1, K + 1), bk = cb_bidx(K + 1, K);
                 cb_sub_abh_mfma(s_re + 256 * bk, s_im + 256 * bk, s_re + 256 * bk, s_im + 256 * bk,
                                 s_re + 256 * b1, s_im + 256 * b1, lane);
                 cb_wave_sync();
-                cb_chol_diag(s_re + 256 * b1, s_im + 256 * b1, dall + CB * (K + 1), csw, lane, bad);
+                cb_chol_diag(s_re + 256 * b1, s_im + 256 * b1, dall + CB * (K + 1), s_col, lane, bad);
             }
-        } else {
-            for (int t = wave - 1; t < nt; t += CB_WAVES - 1) {
+        } else if (wave != 4) {
+            for (int t = uw; t < nt; t += UPD) {
                 int ii = 0;
                 while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
                 const int jj = t - ii * (ii + 1) / 2;
