@@ -677,18 +677,23 @@ __global__ void k_lz_expm(LanczosDev* lz, double tau, StepDev* st) {
 // ---------------------------------------------------------------------------
 constexpr int SMALL_THREADS = 1024;
 
-// Two ownerships of the elements i < n <= SMALL_EVOLVE_N.  In the matvec a
-// quad of adjacent lanes shares the elements i = threadIdx.x / 4 +
-// SMALL_GROUPS t, t < SMALL_PER, and the four lanes split the terms of each
-// element (images and operator stacks dealt round-robin), summed by two lane
-// exchanges; the (l, r, p) split of every element is tabulated in LDS once
-// per launch (10 bits each).  The projections give wave k Krylov vector k;
-// the subtractions, norms and scaling give thread i element i.
+// Two ownerships of the elements i < n <= SMALL_EVOLVE_N.  In the matvec
+// four lanes share each element and split its terms (images and operator
+// stacks dealt round-robin), summed by two lane exchanges: lane e + 16 q of
+// wave w (e < 16, q < 4) takes part q of the elements i = e + 16 w +
+// SMALL_GROUPS t, t < SMALL_PER.  Each 16-lane row of a wave then reads 16
+// consecutive entries of one vector and one operator entry (no LDS bank
+// conflicts; the four parts of an element on adjacent lanes had put three
+// vectors 4 KB apart on the same banks).  The (l, r, p) split of every
+// element is tabulated in LDS once per launch (10 bits each).  The
+// projections give wave k Krylov vector k; the subtractions, norms and
+// scaling give thread i element i.
 constexpr int SMALL_SPLIT = 4;
 constexpr int SMALL_GROUPS = SMALL_THREADS / SMALL_SPLIT;
 constexpr int SMALL_PER = (int)(SMALL_EVOLVE_N / SMALL_GROUPS);
 static_assert(SMALL_PER * SMALL_GROUPS == SMALL_EVOLVE_N, "elements must split evenly over the quads");
 static_assert(SMALL_EVOLVE_N == SMALL_THREADS, "one element per thread in the vector passes");
+static_assert(SMALL_SPLIT * 16 == 64 && SMALL_GROUPS == 16 * (SMALL_THREADS / 64), "four 16-lane parts per wave");
 static_assert(SMALL_EVOLVE_N <= 1024, "leg dimensions must fit the 10-bit fields of the index table");
 
 // acc += sum_q op[o + D q] src[base + sq q], q < D (complex, planar op of D^2
@@ -711,7 +716,7 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
                              int DP, int sL, int sR, const int* sidx, const double* x, double* S, double* y) {
     const int n = DL * DR * DP;
     const int nz = (W && sR > 0) ? sR : 0;
-    const int q = threadIdx.x & (SMALL_SPLIT - 1), g = threadIdx.x / SMALL_SPLIT;
+    const int q = (threadIdx.x >> 4) & (SMALL_SPLIT - 1), g = (threadIdx.x & 15) + 16 * (threadIdx.x >> 6);
     // images: lane q of a quad forms images k = q, q + 4, ... of its elements
     for (int k = q; k < sL + nz; k += SMALL_SPLIT) {
         const bool left = k < sL;
@@ -752,11 +757,11 @@ __device__ void small_matvec(const double* L, const double* Rr, const double* B,
                     small_term(W + 2 * DP * DP * k, DP, p, k == 0 ? x : S + 2 * n * (k - 1), n,
                                i - DL * DR * p, DL * DR, ar, ai);
         }
-        // every lane of the quad shares i, so all four take part
-        ar += __shfl_xor(ar, 1, 64);
-        ai += __shfl_xor(ai, 1, 64);
-        ar += __shfl_xor(ar, 2, 64);
-        ai += __shfl_xor(ai, 2, 64);
+        // the four lanes of element i (16 apart) all take part
+        ar += __shfl_xor(ar, 16, 64);
+        ai += __shfl_xor(ai, 16, 64);
+        ar += __shfl_xor(ar, 32, 64);
+        ai += __shfl_xor(ai, 32, 64);
         if (q == 0 && i < n) {
             y[i] = ar;
             y[n + i] = ai;
