@@ -1564,13 +1564,18 @@ __device__ inline cb_d4 cb_mfma(double a, double b, cb_d4 c) {
 
 // O -= A B^H on a 16 x 16 block by one wave with the FP64 matrix cores.
 // Fragments: A lane l -> A[l%16][k], B lane l -> B[k][l%16], k = kk + l/16;
-// the output register r of lane l is row l/16 + 4 r, column l%16.
+// the output register r of lane l is row l/16 + 4 r, column l%16.  The
+// products are formed transposed (B as the first operand, A^T as the
+// second), so that lane l holds O[l%16][l/16 + 4 r]: the 16 lanes of a row
+// group then touch 16 consecutive entries of a column of O in LDS, where
+// the untransposed layout strode 16 entries and put them on one bank.
 __device__ inline void cb_sub_abh_mfma(const double* Ar, const double* Ai, const double* Br, const double* Bi,
                                        double* Or, double* Oi, int lane) {
     const int m = lane & 15, q = lane >> 4;
-    // four independent accumulator chains, so that consecutive matrix-core
-    // operations never wait on each other's result
-    cb_d4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0}, er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
+    // three real products per complex product (Gauss): with C = conj(B),
+    // P1 = Ar Cr^T, P2 = Ai Ci^T, P3 = (Ar + Ai)(Cr + Ci)^T, Re = P1 - P2 and
+    // Im = P3 - P1 - P2; independent accumulator chains
+    cb_d4 d1 = {0, 0, 0, 0}, d2 = {0, 0, 0, 0}, d3 = {0, 0, 0, 0};
     double ar[4], ai[4], br[4], bi[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -1582,16 +1587,15 @@ __device__ inline void cb_sub_abh_mfma(const double* Ar, const double* Ai, const
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        dr = cb_mfma(ar[t], br[t], dr);
-        di = cb_mfma(ai[t], br[t], di);
-        er = cb_mfma(ai[t], bi[t], er);
-        ei = cb_mfma(-ar[t], bi[t], ei);
+        d1 = cb_mfma(br[t], ar[t], d1);                    // P1^T
+        d2 = cb_mfma(-bi[t], ai[t], d2);                   // P2^T
+        d3 = cb_mfma(br[t] - bi[t], ar[t] + ai[t], d3);    // P3^T
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int o = (q + 4 * r) + CB * m;
-        Or[o] -= dr[r] + er[r];
-        Oi[o] -= di[r] + ei[r];
+        const int o = m + CB * (q + 4 * r);
+        Or[o] -= d1[r] - d2[r];
+        Oi[o] -= d3[r] - d1[r] - d2[r];
     }
 }
 
@@ -1772,14 +1776,6 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                 s_im[e] = gim[q];
             }
         }
-        // blocks strictly above the diagonal of an in-place inverse are zero:
-        // rows 0 .. 16 (j / 16) - 1 of column j
-        if (direct)
-            for (int j = wave; j < D; j += CB_WAVES)
-                for (int i = lane; i < CB * (j / CB); i += 64) {
-                    Linv[i + (int64_t)D * j] = 0.0;
-                    Linv[DD + i + (int64_t)D * j] = 0.0;
-                }
     }
     __syncthreads();
     int bad = 0;
@@ -1826,7 +1822,8 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
         // trailing update A_IJ -= L_IK L_JK^H (K < J <= I); wave 0 first updates
         // the next diagonal block and factors it (look-ahead).  Wave 4, which
         // shares wave 0's SIMD, takes no update blocks, so the factorization's
-        // serial chain has that SIMD to itself; waves 1-3 and 5-7 share the rest
+        // serial chain has that SIMD to itself (it clears the upper blocks of
+        // the output once, global stores only); waves 1-3 and 5-7 share the rest
         const int m = NB - K - 1, nt = m * (m + 1) / 2;
         constexpr int UPD = CB_WAVES - 2;
         const int uw = wave < 4 ? wave - 1 : wave - 2;
@@ -1838,7 +1835,27 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                 cb_wave_sync();
                 cb_chol_diag(s_re + 256 * b1, s_im + 256 * b1, dall + CB * (K + 1), s_col, lane, bad);
             }
-        } else if (wave != 4) {
+        } else if (wave == 4) {
+            // meanwhile: the blocks (I, J), I < J, of an in-place inverse are
+            // zero; the NB (NB - 1) / 2 of them, in order J, then I, are spread
+            // over the iterations, ceil(that / NB) per iteration (lane l: row
+            // l % 16 of columns 4 s + l / 16, four 128-byte segments a store)
+            if (direct) {
+                const int nup = NB * (NB - 1) / 2, per = (nup + NB - 1) / NB;
+                for (int u = K * per; u < nup && u < (K + 1) * per; ++u) {
+                    int J = 1;
+                    while (J * (J + 1) / 2 <= u) ++J;
+                    const int I = u - J * (J - 1) / 2;
+                    const int i = CB * I + (lane & 15);
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int j = CB * J + 4 * s4 + (lane >> 4);
+                        Linv[i + (int64_t)D * j] = 0.0;
+                        Linv[DD + i + (int64_t)D * j] = 0.0;
+                    }
+                }
+            }
+        } else {
             for (int t = uw; t < nt; t += UPD) {
                 int ii = 0;
                 while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
@@ -1857,7 +1874,10 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
     if (wave < NB)
         cb_inv_diag(s_re + 256 * cb_bidx(wave, wave), s_im + 256 * cb_bidx(wave, wave), dall + CB * wave,
                     Xr + CB * wave + (int64_t)Dp * CB * wave, Xi + CB * wave + (int64_t)Dp * CB * wave, Dp, csw, lane);
-    // R = L^H (upper): R[k, a] = conj(L[a, k])
+    // R = L^H (upper): R[k, a] = conj(L[a, k]); lanes over k, so that a
+    // store writes 512 contiguous bytes of a column of R (reading by 16 x 16
+    // blocks instead, conflict-free in LDS but with 32-byte store segments,
+    // measured slower)
     for (int a = wave; a < D; a += CB_WAVES)
         for (int k = lane; k < D; k += 64) {
             double vr = 0.0, vi = 0.0;
@@ -1907,8 +1927,10 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                     xa_r[j] = Xr[g];
                     xa_i[j] = Xi[g];
                 }
-                // four independent accumulator chains (T = tr + ur, ti + ui)
-                cb_d4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0}, ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+                // T = sum_t L_{I,J+t} X_{J+t,J}, three real products per complex
+                // product (Gauss): P1 = Lr Xr, P2 = Li Xi, P3 = (Lr + Li)(Xr + Xi),
+                // Re T = P1 - P2, Im T = P3 - P1 - P2
+                cb_d4 p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
                 for (int t = 0; t < dl; ++t) {
                     const double* Lr = s_re + 256 * cb_bidx(I, J + t);
@@ -1917,25 +1939,21 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
                     for (int j = 0; j < 4; ++j) {
                         const int ia = m + CB * (4 * j + q);
                         const double lr = Lr[ia], li = Li[ia], br = xb_r[4 * t + j], bi = xb_i[4 * t + j];
-                        tr = cb_mfma(lr, br, tr);
-                        ti = cb_mfma(lr, bi, ti);
-                        ur = cb_mfma(-li, bi, ur);
-                        ui = cb_mfma(li, br, ui);
+                        p1 = cb_mfma(lr, br, p1);
+                        p2 = cb_mfma(li, bi, p2);
+                        p3 = cb_mfma(lr + li, br + bi, p3);
                     }
                 }
-                tr += ur;
-                ti += ui;
-                // X_IJ = - X_II T
-                cb_d4 orr = {0, 0, 0, 0}, oi = {0, 0, 0, 0}, o2r = {0, 0, 0, 0}, o2i = {0, 0, 0, 0};
+                const cb_d4 tr = p1 - p2, ti = p3 - p1 - p2;
+                // X_IJ = - X_II T, the same three-product form
+                cb_d4 q1 = {0, 0, 0, 0}, q2 = {0, 0, 0, 0}, q3 = {0, 0, 0, 0};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    orr = cb_mfma(-xa_r[j], tr[j], orr);
-                    oi = cb_mfma(-xa_r[j], ti[j], oi);
-                    o2r = cb_mfma(xa_i[j], ti[j], o2r);
-                    o2i = cb_mfma(-xa_i[j], tr[j], o2i);
+                    q1 = cb_mfma(xa_r[j], tr[j], q1);
+                    q2 = cb_mfma(xa_i[j], ti[j], q2);
+                    q3 = cb_mfma(xa_r[j] + xa_i[j], tr[j] + ti[j], q3);
                 }
-                orr += o2r;
-                oi += o2i;
+                const cb_d4 orr = q2 - q1, oi = q1 + q2 - q3;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t g = (CB * I + q + 4 * r) + (int64_t)Dp * (CB * J + m);
