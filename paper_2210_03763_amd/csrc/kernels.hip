@@ -1756,24 +1756,36 @@ __global__ __launch_bounds__(CB_THREADS) void k_chol_blk(const double* G, int D,
         // thread is issued before its first LDS store
         constexpr int LQ = CB_NBLK * 256 / CB_THREADS;
         static_assert(LQ * CB_THREADS == CB_NBLK * 256, "blocks must split evenly over the threads");
-        double gr[LQ], gim[LQ];
+        if (nbl == 1) {   // D <= 16: one block, one entry per thread
+            if (tid < 256) {
+                const int gi = tid & 15, gj = tid >> 4;
+                const bool in = gi < D && gj < D;
+                s_re[tid] = in ? G[gi + (int64_t)D * gj] : (gi == gj ? 1.0 : 0.0);
+                s_im[tid] = in ? G[DD + gi + (int64_t)D * gj] : 0.0;
+            }
+        } else {
+            double gr[LQ], gim[LQ];
 #pragma unroll
-        for (int q = 0; q < LQ; ++q) {
-            const int e = tid + CB_THREADS * q, b = e >> 8, rc = e & 255;
-            int I = 0;
-            while ((I + 1) * (I + 2) / 2 <= b) ++I;
-            const int J = b - I * (I + 1) / 2;
-            const int gi = CB * I + (rc & 15), gj = CB * J + (rc >> 4);
-            const bool in = b < nbl && gi < D && gj < D;
-            gr[q] = in ? G[gi + (int64_t)D * gj] : (gi == gj ? 1.0 : 0.0);
-            gim[q] = in ? G[DD + gi + (int64_t)D * gj] : 0.0;
-        }
+            for (int q = 0; q < LQ; ++q) {
+                const int e = tid + CB_THREADS * q, b = e >> 8, rc = e & 255;
+                // block row of packed block b: the largest I with I (I + 1) / 2 <= b,
+                // floor((sqrt(8 b + 1) - 1) / 2); for b < 36 the value stays at
+                // least 0.11 below the next integer, so the 0.05 guard absorbs any
+                // rounding of the root at the perfect squares
+                const int I = (int)((sqrtf((float)(8 * b + 1)) - 1.0f) * 0.5f + 0.05f);
+                const int J = b - I * (I + 1) / 2;
+                const int gi = CB * I + (rc & 15), gj = CB * J + (rc >> 4);
+                const bool in = b < nbl && gi < D && gj < D;
+                gr[q] = in ? G[gi + (int64_t)D * gj] : (gi == gj ? 1.0 : 0.0);
+                gim[q] = in ? G[DD + gi + (int64_t)D * gj] : 0.0;
+            }
 #pragma unroll
-        for (int q = 0; q < LQ; ++q) {
-            const int e = tid + CB_THREADS * q;
-            if ((e >> 8) < nbl) {
-                s_re[e] = gr[q];
-                s_im[e] = gim[q];
+            for (int q = 0; q < LQ; ++q) {
+                const int e = tid + CB_THREADS * q;
+                if ((e >> 8) < nbl) {
+                    s_re[e] = gr[q];
+                    s_im[e] = gim[q];
+                }
             }
         }
     }
