@@ -551,14 +551,14 @@ __global__ __launch_bounds__(256) void k_lz_beta(const double* partial, int nb, 
 
 // y = exp(-i tau H) e_1 for the m_eff x m_eff projection H of the Krylov
 // basis: the Taylor series of exp(B/s), B = -i tau H, applied s times to the
-// vector, with s chosen so that ||B/s||_1 <= 1/4 (terms are summed until they
-// stop changing the result in double precision).  H is the real symmetric
-// tridiagonal (alpha, beta) of a Lanczos basis, or the complex upper
-// Hessenberg matrix of an Arnoldi basis (columns in hs, subdiagonal beta)
-// when lz->nonherm.  The first wave does all of it, lane t holding row t of
-// H and element t of the vectors (products with H by lane shuffles, the
-// stopping test by a wave reduction); the other waves of the block only meet
-// it at the closing barrier.
+// vector, with s chosen so that ||B/s||_1 <= 1/4 and as many terms as make
+// the remainder bound of the series fall below double precision.  H is the
+// real symmetric tridiagonal (alpha, beta) of a Lanczos basis, or the complex
+// upper Hessenberg matrix of an Arnoldi basis (columns in hs, subdiagonal
+// beta) when lz->nonherm.  The first wave does all of it, lane t holding row
+// t of H and element t of the vectors (products with H by lane shuffles, the
+// norm by one wave reduction); the other waves of the block only meet it at
+// the closing barrier.
 
 // entry (row, col) of the projection (re, im), zero outside m x m
 __device__ inline double2 lz_h_entry(const LanczosDev* lz, bool herm, int m, int row, int col) {
@@ -619,10 +619,20 @@ __device__ __forceinline__ void lz_expm_hessenberg(LanczosDev* lz, double tau, S
         int ns = (int)ceil(nrm / 0.25);
         if (ns < 1) ns = 1;
         const double h = tau / ns;
+        // number of Taylor terms K: with theta = ||h H||_1 <= 1/4 the
+        // remainder after K terms is at most theta^(K+1) / (K+1)! e^theta
+        // (e^theta < 1.3) of the vector, kept below 1e-18 (the same K in
+        // every lane, no reductions inside the series)
+        const double theta = nrm / ns;
+        int K = 0;
+        for (double a = 1.0; K < 40; ++K) {
+            a *= theta / (K + 1);   // theta^(K+1) / (K+1)!
+            if (1.3 * a <= 1e-18) break;
+        }
         double vr = t == 0 ? 1.0 : 0.0, vi = 0.0;
         for (int rep = 0; rep < ns; ++rep) {
             double tr = vr, ti = vi, wr = vr, wi = vi;
-            for (int k = 1; k <= 40; ++k) {
+            for (int k = 1; k <= K; ++k) {
                 // term <- (-i h H term) / k
                 double sr = 0, si = 0;
                 if (herm) {
@@ -645,9 +655,6 @@ __device__ __forceinline__ void lz_expm_hessenberg(LanczosDev* lz, double tau, S
                     wr += tr;
                     wi += ti;
                 }
-                const double tmax = wave_max(t < m ? fabs(tr) + fabs(ti) : 0.0);
-                const double wmax = wave_max(t < m ? fabs(wr) + fabs(wi) : 0.0);
-                if (tmax <= 1e-18 * wmax) break;   // the same decision in every lane
             }
             vr = wr;
             vi = wi;
